@@ -1,0 +1,250 @@
+"""CPU oracle for node2vec second-order walks (test infrastructure only).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` import this package.  It wraps ``oracle.c`` (plain C, built with
+gcc by ``oracle/build.py``) and shares nothing with the GPU library.  See the
+header of ``oracle.c`` for the definitions each function follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SENT = 0xFFFFFFFF
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(LIB_PATH)
+    u32, u64, i32, dbl, vp = C.c_uint32, C.c_uint64, C.c_int, C.c_double, C.c_void_p
+    lib.or_philox.argtypes = [u32, u32, vp, vp]
+    lib.or_philox.restype = None
+    lib.or_hi64.argtypes = [u64, u64]
+    lib.or_hi64.restype = u64
+    lib.or_rmat_thresholds.argtypes = [dbl, dbl, dbl, vp]
+    lib.or_rmat_thresholds.restype = None
+    lib.or_rmat_raw.argtypes = [u32, dbl, dbl, dbl, u64, u64, u64, vp, vp, i32]
+    lib.or_rmat_raw.restype = None
+    lib.or_pair_weight.argtypes = [u64, u32, u32]
+    lib.or_pair_weight.restype = C.c_uint16
+    lib.or_rmat_csr.argtypes = [u32, u32, dbl, dbl, dbl, u64, vp, vp, vp, u64, vp, i32]
+    lib.or_rmat_csr.restype = i32
+    lib.or_graph_new.argtypes = [vp, vp, vp, u32]
+    lib.or_graph_new.restype = vp
+    lib.or_graph_free.argtypes = [vp]
+    lib.or_graph_free.restype = None
+    lib.or_multipliers.argtypes = [dbl, dbl, vp]
+    lib.or_multipliers.restype = i32
+    lib.or_walk.argtypes = [vp, vp, vp, u64, u64, u32, dbl, dbl, u64, u32, u32, vp, vp, vp, vp, i32]
+    lib.or_walk.restype = i32
+    lib.or_step_hist.argtypes = [vp, u32, u32, u32, u32, u64, dbl, dbl, u64, u32, u32, vp]
+    lib.or_step_hist.restype = i32
+    lib.or_entry_hash.argtypes = [u64, u32, u32, u32]
+    lib.or_entry_hash.restype = u64
+    lib.or_walk_cost.argtypes = [vp, vp, vp, u64, u32, dbl, dbl, u64, u32, u32, vp, vp, vp, i32]
+    lib.or_walk_cost.restype = i32
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def default_threads() -> int:
+    n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+# --------------------------------------------------------------------------
+# primitives
+# --------------------------------------------------------------------------
+def philox(key, ctr):
+    """Philox4x32-10 of one (key[2], ctr[4]) -> 4 words."""
+    k = [int(x) & 0xFFFFFFFF for x in key]
+    c = np.array([int(x) & 0xFFFFFFFF for x in ctr], dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().or_philox(k[0], k[1], _ptr(c), _ptr(out))
+    return [int(x) for x in out]
+
+
+def hi64(x: int, y: int) -> int:
+    return int(_load().or_hi64(x, y))
+
+
+def rmat_thresholds(a, b, c):
+    T = np.zeros(3, dtype=np.uint64)
+    _load().or_rmat_thresholds(a, b, c, _ptr(T))
+    return [int(x) for x in T]
+
+
+def rmat_raw(scale, a, b, c, gseed, e0, count, nthreads=None):
+    """Raw R-MAT edges e0 .. e0+count-1 (before loop removal and symmetrisation)."""
+    u = np.zeros(count, dtype=np.uint32)
+    v = np.zeros(count, dtype=np.uint32)
+    _load().or_rmat_raw(scale, a, b, c, gseed, e0, count, _ptr(u), _ptr(v),
+                        nthreads or default_threads())
+    return u, v
+
+
+def pair_weight(gseed, x, y):
+    return int(_load().or_pair_weight(gseed, x, y))
+
+
+def multipliers(p, q):
+    A = np.zeros(3, dtype=np.uint32)
+    if _load().or_multipliers(p, q, _ptr(A)) != 0:
+        raise ValueError("p and q must be in {0.25, 0.5, 1, 2, 4}")
+    return [int(x) for x in A]
+
+
+def entry_hash(seed, wid, col, x):
+    return int(_load().or_entry_hash(seed, wid, col, x))
+
+
+# --------------------------------------------------------------------------
+# graphs
+# --------------------------------------------------------------------------
+class CSR:
+    """A CSR graph held in numpy arrays (off u64[n+1], adj u32[m], wt u16[m] or None)."""
+
+    def __init__(self, off, adj, wt=None):
+        self.off = np.ascontiguousarray(off, dtype=np.uint64)
+        self.adj = np.ascontiguousarray(adj, dtype=np.uint32)
+        self.wt = None if wt is None else np.ascontiguousarray(wt, dtype=np.uint16)
+        self.n = len(self.off) - 1
+        self.m = int(self.off[-1])
+        self._h = None
+
+    @property
+    def handle(self):
+        if self._h is None:
+            self._h = _load().or_graph_new(_ptr(self.off), _ptr(self.adj), _ptr(self.wt), self.n)
+            if not self._h:
+                raise MemoryError("oracle graph")
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.or_graph_free(self._h)
+            self._h = None
+
+    def degree(self):
+        return np.diff(self.off.astype(np.int64))
+
+    def row(self, v):
+        return self.adj[int(self.off[v]):int(self.off[v + 1])]
+
+    @staticmethod
+    def from_edges(n, edges, weights=None):
+        """Symmetric CSR from undirected edge pairs (dedup, loops dropped).
+
+        weights: optional dict {(min,max): w}."""
+        rows = [set() for _ in range(n)]
+        for a, b in edges:
+            if a == b:
+                continue
+            rows[a].add(b)
+            rows[b].add(a)
+        off = np.zeros(n + 1, dtype=np.uint64)
+        adj = []
+        wt = [] if weights is not None else None
+        for v in range(n):
+            r = sorted(rows[v])
+            adj.extend(r)
+            if wt is not None:
+                wt.extend(weights[(min(v, x), max(v, x))] for x in r)
+            off[v + 1] = off[v] + len(r)
+        return CSR(off, np.array(adj, dtype=np.uint32),
+                   None if wt is None else np.array(wt, dtype=np.uint16))
+
+
+def rmat_csr(scale, edge_factor, a, b, c, gseed, weighted=False, nthreads=None):
+    """CSR of the symmetrised, de-duplicated, loop-free R-MAT graph."""
+    n = 1 << scale
+    cap = 2 * (edge_factor << scale)
+    off = np.zeros(n + 1, dtype=np.uint64)
+    adj = np.zeros(cap, dtype=np.uint32)
+    wt = np.zeros(cap, dtype=np.uint16) if weighted else None
+    m = np.zeros(1, dtype=np.uint64)
+    rc = _load().or_rmat_csr(scale, edge_factor, a, b, c, gseed, _ptr(off), _ptr(adj),
+                             _ptr(wt), cap, _ptr(m), nthreads or default_threads())
+    if rc != 0:
+        raise RuntimeError(f"or_rmat_csr failed ({rc})")
+    mm = int(m[0])
+    adj = adj[:mm].copy()
+    if wt is not None:
+        wt = wt[:mm].copy()
+    return CSR(off, adj, wt)
+
+
+# --------------------------------------------------------------------------
+# walks
+# --------------------------------------------------------------------------
+D_RULE = 1024
+A_CAP = 1024
+
+
+def walk(g: CSR, starts, L, p, q, seed, walk_base=0, wids=None, d_rule=D_RULE, a_cap=A_CAP,
+         want_out=True, want_counts=False, nthreads=None):
+    """Runs the walks; returns dict(out, cnt, checksum, transitions)."""
+    starts = np.ascontiguousarray(starts, dtype=np.uint32)
+    count = len(starts)
+    wid_arr = None if wids is None else np.ascontiguousarray(wids, dtype=np.uint64)
+    out = np.zeros((count, L + 1), dtype=np.uint32) if want_out else None
+    cnt = np.zeros(g.n, dtype=np.uint32) if want_counts else None
+    cs = np.zeros(1, dtype=np.uint64)
+    tr = np.zeros(1, dtype=np.uint64)
+    rc = _load().or_walk(g.handle, _ptr(starts), _ptr(wid_arr), walk_base, count, L, p, q, seed,
+                         d_rule, a_cap, _ptr(out), _ptr(cnt), _ptr(cs), _ptr(tr),
+                         nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("bad walk arguments (p, q or a start id)")
+    return {"out": out, "cnt": cnt, "checksum": int(cs[0]), "transitions": int(tr[0])}
+
+
+def step_hist(g: CSR, t, v, s, draws, p, q, seed, wid0=0, d_rule=D_RULE, a_cap=A_CAP):
+    """Counts of each neighbour index of v chosen over `draws` single moves at (t, v, s)."""
+    d = int(g.off[v + 1] - g.off[v])
+    hist = np.zeros(d, dtype=np.uint64)
+    rc = _load().or_step_hist(g.handle, t, v, s, wid0, draws, p, q, seed, d_rule, a_cap, _ptr(hist))
+    if rc != 0:
+        raise ValueError("bad step arguments")
+    return hist
+
+
+def walk_cost(g: CSR, starts, wids, L, p, q, seed, d_rule=D_RULE, a_cap=A_CAP, nthreads=None):
+    """(algorithmic bytes, moves, moves at vertices above d_rule) summed over the walks."""
+    starts = np.ascontiguousarray(starts, dtype=np.uint32)
+    wids = np.ascontiguousarray(wids, dtype=np.uint64)
+    b = np.zeros(1, dtype=np.uint64)
+    s = np.zeros(1, dtype=np.uint64)
+    h = np.zeros(1, dtype=np.uint64)
+    rc = _load().or_walk_cost(g.handle, _ptr(starts), _ptr(wids), len(starts), L, p, q, seed,
+                              d_rule, a_cap, _ptr(b), _ptr(s), _ptr(h), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("bad cost arguments")
+    return int(b[0]), int(s[0]), int(h[0])
+
+
+def checksum_of(out, seed, walk_ids):
+    """Visit counts and checksum of a walk matrix, entry by entry (slow; small inputs)."""
+    total = 0
+    for i, row in enumerate(out):
+        wid = int(walk_ids[i]) & 0xFFFFFFFF
+        for col, x in enumerate(row):
+            if int(x) == SENT:
+                break
+            total = (total + entry_hash(seed, wid, col, int(x))) & 0xFFFFFFFFFFFFFFFF
+    return total
