@@ -1,0 +1,65 @@
+"""Planted mistakes in copies of the oracle are caught by the pins (CPU only).
+
+Each case edits one line of a private copy of oracle.c, builds it under /tmp,
+and runs a subset of the pin tests against it in a subprocess; the subset
+must fail.  The committed oracle is never modified.
+"""
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTATIONS = [
+    ("swap common and outward multipliers",
+     "if (or_has_edge(g, t, x)) return w * A[1];", "if (or_has_edge(g, t, x)) return w * A[2];"),
+    ("drop the return bias",
+     "if (x == t) return w * A[0];", "if (x == t) return w * A[1];"),
+    ("first move uses second-order weights",
+     "if (s == 0) return w;", "if (s == 99) return w;"),
+    ("inverse CDF off by one",
+     "if (P > target) return g->adj[g->off[v] + j];", "if (P >= target) return g->adj[g->off[v] + j];"),
+    ("envelope too small",
+     "if (A[2] > amax) amax = A[2];\n        uint64_t E = (uint64_t)g->wmax[v] * (s == 0 ? 1u : amax);",
+     "if (A[2] > amax) amax = A[2];\n        uint64_t E = (uint64_t)g->wmax[v] * (s == 0 ? 1u : A[1]);"),
+    ("wrong Philox multiplier",
+     "uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;", "uint64_t p1 = (uint64_t)0xCD9E8D57u * c1;"),
+    ("R-MAT row and column bits transposed",
+     "u |= (quad >> 1) << (scale - 1 - l);", "u |= (quad & 1u) << (scale - 1 - l);"),
+    ("weight of the wrong pair",
+     "ph(gseed, lo, hi, 0, 2, r);", "ph(gseed, lo, lo, 0, 2, r);"),
+]
+
+TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_rmat.py", "tests/test_oracle_law.py",
+         "tests/test_oracle_invariants.py"]
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    tmp = tempfile.mkdtemp(prefix="n2v_mut_")
+    try:
+        pkg = os.path.join(tmp, "oracle")
+        shutil.copytree(os.path.join(ROOT, "oracle"), pkg,
+                        ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+        with open(os.path.join(pkg, "oracle.c"), "w") as f:
+            f.write(src.replace(old, new))
+        subprocess.check_call([sys.executable, os.path.join(pkg, "build.py")],
+                              stdout=subprocess.DEVNULL)
+        tdir = os.path.join(tmp, "tests")
+        shutil.copytree(os.path.join(ROOT, "tests"), tdir,
+                        ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutations.py"))
+        env = dict(os.environ, PYTHONPATH=tmp)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            "-m", "not gpu"] + [os.path.join(tmp, t) for t in TESTS],
+                           cwd=tmp, env=env, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                           timeout=600)
+        assert r.returncode != 0, f"mutation '{name}' was not caught:\n" + r.stdout.decode()[-2000:]
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
