@@ -1,0 +1,177 @@
+// common.hpp -- internal definitions shared by the HIP sources of the walk
+// engine: error reporting, the device graph view, the counter RNG, 128-bit
+// multiply-high and wavefront (64-lane) primitives for CDNA.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/n2v.h"
+
+namespace n2v {
+
+constexpr uint32_t SENT = 0xFFFFFFFFu;
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- errors
+int set_error(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+#define N2V_HIP(call)                                              \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return ::n2v::hip_fail(e_, #call);   \
+    } while (0)
+
+// ------------------------------------------------------------ graph view
+// Per-vertex record: row offset, degree and largest weight of the row.
+// One 16-byte aligned load gives everything a move needs about a vertex.
+struct alignas(16) VRec {
+    uint64_t off;
+    uint32_t deg;
+    uint32_t wmax;
+};
+
+struct DevGraph {
+    const VRec *vrec;      // n
+    const uint2 *erec;     // m: (neighbour x, position of the reverse entry in N(x) or SENT)
+    const uint32_t *adj;   // m, rows strictly ascending
+    const uint16_t *wt;    // m, or null for an unweighted graph
+    const uint64_t *wsum;  // n: row weight sums (weighted graphs only)
+    uint32_t *status;      // device flags: bit 0 = a start id was out of range
+    uint32_t n;
+    uint64_t m;
+    uint32_t d_rule;
+    uint32_t a_cap;
+};
+
+// ------------------------------------------------------------ counter RNG
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+struct R4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ R4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                                     uint32_t c3)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return R4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint64_t hi64(uint64_t x, uint64_t y) { return __umul64hi(x, y); }
+
+__device__ __forceinline__ uint64_t join64(uint32_t hi, uint32_t lo)
+{
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// --------------------------------------------------------- wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// LDS written by some lanes of a wave becomes visible to the other lanes.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t shfl32(uint32_t v, int src) { return __shfl(v, src, WAVE); }
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+{
+    uint32_t lo = __shfl((uint32_t)v, src, WAVE);
+    uint32_t hi = __shfl((uint32_t)(v >> 32), src, WAVE);
+    return join64(hi, lo);
+}
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d)
+{
+    uint32_t lo = __shfl_up((uint32_t)v, d, WAVE);
+    uint32_t hi = __shfl_up((uint32_t)(v >> 32), d, WAVE);
+    return join64(hi, lo);
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m)
+{
+    uint32_t lo = __shfl_xor((uint32_t)v, m, WAVE);
+    uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, WAVE);
+    return join64(hi, lo);
+}
+
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint64_t o = shfl_up64(v, d);
+        if (l >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor64(v, m);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ int first_lane(uint64_t mask) { return __ffsll((unsigned long long)mask) - 1; }
+
+// Lower bound of x in a[lo, hi) (global memory); returns the index.
+__device__ __forceinline__ uint64_t lower_bound_g(const uint32_t *__restrict__ a, uint64_t lo, uint64_t hi,
+                                                  uint32_t x)
+{
+    while (lo < hi) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool contains_g(const uint32_t *__restrict__ a, uint64_t lo, uint64_t hi, uint32_t x)
+{
+    const uint64_t p = lower_bound_g(a, lo, hi, x);
+    return p < hi && a[p] == x;
+}
+
+}  // namespace n2v
+
+// Host-side graph handle.
+struct n2v_graph {
+    n2v::DevGraph dg;
+    const uint64_t *off;
+    int weighted;
+    int validate;
+    int device;
+    bool has_tuned;
+    n2v_exec_opts tuned;
+};

@@ -1,0 +1,229 @@
+// graph.hip -- graph handle: validation of a caller's CSR and the derived
+// arrays the walk kernels read (per-vertex records, reverse-entry positions,
+// row weight sums and maxima).
+#include <stdlib.h>
+
+#include "prims.hpp"
+
+namespace n2v {
+
+namespace {
+
+enum : uint32_t { BAD_OFF = 1, BAD_ROW = 2, BAD_ASYM = 4, BAD_ENDS = 8 };
+
+__global__ __launch_bounds__(256) void k_validate(const uint64_t *__restrict__ off, const uint32_t *__restrict__ adj,
+                                                  const uint16_t *__restrict__ wt, uint32_t n, uint64_t m,
+                                                  uint32_t *__restrict__ bad)
+{
+    const int l = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / WAVE;
+    if (wave == 0 && l == 0 && (off[0] != 0 || off[n] != m)) atomicOr(bad, BAD_ENDS);
+    uint32_t flags = 0;
+    for (uint64_t v = wave; v < n; v += nw) {
+        const uint64_t lo = off[v], hi = off[v + 1];
+        if (hi < lo || hi > m) {
+            flags |= BAD_OFF;
+            continue;
+        }
+        for (uint64_t e = lo + l; e < hi; e += WAVE) {
+            const uint32_t x = adj[e];
+            if (x >= n || x == (uint32_t)v) flags |= BAD_ROW;
+            if (e > lo && adj[e - 1] >= x) flags |= BAD_ROW;
+            if (wt && wt[e] == 0) flags |= BAD_ROW;
+        }
+    }
+    if (flags) atomicOr(bad, flags);
+}
+
+__global__ __launch_bounds__(256) void k_derive(const uint64_t *__restrict__ off, const uint32_t *__restrict__ adj,
+                                                const uint16_t *__restrict__ wt, uint32_t n, VRec *__restrict__ vrec,
+                                                uint2 *__restrict__ erec, uint64_t *__restrict__ wsum,
+                                                uint32_t *__restrict__ bad, int check_sym)
+{
+    const int l = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / WAVE;
+    uint32_t flags = 0;
+    for (uint64_t v = wave; v < n; v += nw) {
+        const uint64_t lo = off[v], hi = off[v + 1];
+        uint32_t wm = 0;
+        uint64_t ws = 0;
+        for (uint64_t e = lo + l; e < hi; e += WAVE) {
+            const uint32_t x = adj[e];
+            const uint64_t xlo = off[x], xhi = off[x + 1];
+            const uint64_t p = lower_bound_g(adj, xlo, xhi, (uint32_t)v);
+            const bool found = p < xhi && adj[p] == (uint32_t)v;
+            if (!found && check_sym) flags |= BAD_ASYM;
+            erec[e] = make_uint2(x, found ? (uint32_t)(p - xlo) : SENT);
+            const uint32_t w = wt ? wt[e] : 1u;
+            wm = w > wm ? w : wm;
+            ws += w;
+        }
+#pragma unroll
+        for (int msk = 32; msk >= 1; msk >>= 1) {
+            const uint32_t o = __shfl_xor(wm, msk, WAVE);
+            wm = o > wm ? o : wm;
+        }
+        ws = wave_sum(ws);
+        if (l == 0) {
+            VRec r;
+            r.off = lo;
+            r.deg = (uint32_t)(hi - lo);
+            r.wmax = hi > lo ? wm : 0u;
+            vrec[v] = r;
+            if (wsum) wsum[v] = ws;
+        }
+    }
+    if (flags) atomicOr(bad, flags);
+}
+
+__global__ void k_zero_u32(uint32_t *p, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+struct GraphLayout {
+    VRec *vrec;
+    uint2 *erec;
+    uint64_t *wsum;
+    uint32_t *status;
+};
+
+size_t graph_layout(uint32_t n, uint64_t m, int weighted, void *ws, size_t ws_bytes, GraphLayout *L)
+{
+    Carver c(ws, ws_bytes);
+    L->status = c.take<uint32_t>(64);
+    L->vrec = c.take<VRec>((uint64_t)n + 1);
+    L->erec = c.take<uint2>(m ? m : 1);
+    L->wsum = weighted ? c.take<uint64_t>((uint64_t)n + 1) : nullptr;
+    return c.total();
+}
+
+uint32_t grid_for_waves(uint64_t waves)
+{
+    uint64_t blocks = (waves + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    return (uint32_t)blocks;
+}
+
+}  // namespace
+
+}  // namespace n2v
+
+using namespace n2v;
+
+extern "C" void n2v_graph_opts_default(n2v_graph_opts *o)
+{
+    if (!o) return;
+    o->d_rule = 1024;
+    o->a_cap = 1024;
+    o->validate = 1;
+}
+
+extern "C" int n2v_graph_workspace(uint32_t n, uint64_t m, int weighted, size_t *ws_bytes)
+{
+    if (!ws_bytes) return set_error(N2V_EINVAL, "n2v_graph_workspace: null ws_bytes");
+    if (n == 0 || n > 0xFFFFFFFEu) return set_error(N2V_EINVAL, "n2v_graph_workspace: n out of range");
+    GraphLayout L;
+    *ws_bytes = graph_layout(n, m, weighted, nullptr, 0, &L);
+    return N2V_OK;
+}
+
+extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const uint16_t *wt, uint32_t n, uint64_t m,
+                                const n2v_graph_opts *opts, void *ws, size_t ws_bytes, void *stream,
+                                n2v_graph **out)
+{
+    if (!out) return set_error(N2V_EINVAL, "n2v_graph_create: null out");
+    *out = nullptr;
+    if (!off || (!adj && m) || !ws) return set_error(N2V_EINVAL, "n2v_graph_create: null pointer");
+    if (n == 0 || n > 0xFFFFFFFEu) return set_error(N2V_EINVAL, "n2v_graph_create: n out of range");
+    if (((uintptr_t)ws & 255) != 0) return set_error(N2V_EINVAL, "n2v_graph_create: workspace not 256-byte aligned");
+    n2v_graph_opts o;
+    n2v_graph_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.a_cap < 1) return set_error(N2V_EINVAL, "n2v_graph_create: a_cap must be >= 1");
+    GraphLayout L;
+    size_t need = graph_layout(n, m, wt != nullptr, ws, ws_bytes, &L);
+    if (need > ws_bytes) return set_error(N2V_ENOMEM, "n2v_graph_create: workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, L.status, 64u);
+    N2V_HIP(hipGetLastError());
+    if (o.validate >= 1) {
+        hipLaunchKernelGGL(k_validate, dim3(grid_for_waves(n)), dim3(256), 0, st, off, adj, wt, n, m, L.status + 1);
+        N2V_HIP(hipGetLastError());
+        uint32_t bad = 0;
+        N2V_HIP(hipMemcpyAsync(&bad, L.status + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        N2V_HIP(hipStreamSynchronize(st));
+        if (bad)
+            return set_error(N2V_EGRAPH,
+                             "n2v_graph_create: CSR violates the contract (flags 0x%x: 1 offsets, 2 row order/loop/"
+                             "id/weight, 8 off[0] or off[n])",
+                             bad);
+    }
+    hipLaunchKernelGGL(k_derive, dim3(grid_for_waves(n)), dim3(256), 0, st, off, adj, wt, n, L.vrec, L.erec, L.wsum,
+                       L.status + 1, o.validate >= 2 ? 1 : 0);
+    N2V_HIP(hipGetLastError());
+    if (o.validate >= 2) {
+        uint32_t bad = 0;
+        N2V_HIP(hipMemcpyAsync(&bad, L.status + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        N2V_HIP(hipStreamSynchronize(st));
+        if (bad) return set_error(N2V_EGRAPH, "n2v_graph_create: CSR is not symmetric (flags 0x%x)", bad);
+    }
+    n2v_graph *g = (n2v_graph *)calloc(1, sizeof(n2v_graph));
+    if (!g) return set_error(N2V_ENOMEM, "n2v_graph_create: host allocation failed");
+    g->dg.vrec = L.vrec;
+    g->dg.erec = L.erec;
+    g->dg.adj = adj;
+    g->dg.wt = wt;
+    g->dg.wsum = L.wsum;
+    g->dg.status = L.status;
+    g->dg.n = n;
+    g->dg.m = m;
+    g->dg.d_rule = o.d_rule;
+    g->dg.a_cap = o.a_cap;
+    g->off = off;
+    g->weighted = wt != nullptr;
+    g->validate = o.validate;
+    if (hipGetDevice(&g->device) != hipSuccess) g->device = 0;
+    g->has_tuned = false;
+    *out = g;
+    return N2V_OK;
+}
+
+extern "C" int n2v_graph_destroy(n2v_graph *g)
+{
+    free(g);
+    return N2V_OK;
+}
+
+extern "C" int n2v_graph_info(const n2v_graph *g, uint32_t *n, uint64_t *m, uint32_t *d_rule, uint32_t *a_cap,
+                              int *weighted)
+{
+    if (!g) return set_error(N2V_EINVAL, "n2v_graph_info: null graph");
+    if (n) *n = g->dg.n;
+    if (m) *m = g->dg.m;
+    if (d_rule) *d_rule = g->dg.d_rule;
+    if (a_cap) *a_cap = g->dg.a_cap;
+    if (weighted) *weighted = g->weighted;
+    return N2V_OK;
+}
+
+extern "C" int n2v_graph_check(const n2v_graph *g, void *stream)
+{
+    if (!g) return set_error(N2V_EINVAL, "n2v_graph_check: null graph");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t flag = 0;
+    N2V_HIP(hipMemcpyAsync(&flag, g->dg.status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    N2V_HIP(hipStreamSynchronize(st));
+    if (flag) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, g->dg.status, 1u);
+        N2V_HIP(hipGetLastError());
+        N2V_HIP(hipStreamSynchronize(st));
+        if (flag & 2u) return set_error(N2V_EDEVICE, "n2v_graph_check: internal error in an inverse-CDF move");
+        return set_error(N2V_EINVAL, "n2v_graph_check: a walk had a start id >= n");
+    }
+    return N2V_OK;
+}

@@ -1,0 +1,133 @@
+// tune.hip -- autotuner of the persistent kernel's execution parameters.
+//
+// It times the persistent kernel on a seeded sample of walks (start vertices
+// drawn uniformly over all vertices, the same distribution as walks from
+// every vertex) under candidate settings of the degree thresholds, the
+// sparse/dense hub cost weight and the grid size, by coordinate descent, and
+// stores the fastest setting in the graph.  Execution parameters never change
+// outputs, so tuning cannot change any result.
+#include <vector>
+
+#include "prims.hpp"
+#include "walk.hpp"
+
+namespace n2v {
+
+namespace {
+
+__global__ void k_sample_starts(uint32_t *starts, uint32_t count, uint32_t n, uint32_t k0)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const R4 r = philox(k0, 0x6e327674u, i, 0u, 0u, 7u);
+        starts[i] = (uint32_t)(((uint64_t)r.x * n) >> 32);
+    }
+}
+
+struct TuneLayout {
+    uint32_t *starts;
+    uint32_t *out;
+};
+
+size_t tune_layout(uint32_t n_walks, uint32_t L, void *ws, size_t ws_bytes, TuneLayout *T)
+{
+    Carver c(ws, ws_bytes);
+    T->starts = c.take<uint32_t>(n_walks);
+    T->out = c.take<uint32_t>((uint64_t)n_walks * (L + 1));
+    return c.total();
+}
+
+}  // namespace
+
+}  // namespace n2v
+
+using namespace n2v;
+
+extern "C" int n2v_autotune_workspace(const n2v_graph *g, uint32_t n_walks, uint32_t L, size_t *ws_bytes)
+{
+    if (!g || !ws_bytes || n_walks == 0 || L == 0) return set_error(N2V_EINVAL, "n2v_autotune_workspace: bad argument");
+    TuneLayout T;
+    *ws_bytes = tune_layout(n_walks, L, nullptr, 0, &T);
+    return N2V_OK;
+}
+
+extern "C" int n2v_autotune(n2v_graph *g, uint32_t n_walks, uint32_t L, float p, float q, void *ws, size_t ws_bytes,
+                            void *stream, n2v_exec_opts *best, double *best_ms)
+{
+    if (!g || !ws || n_walks == 0 || L == 0) return set_error(N2V_EINVAL, "n2v_autotune: bad argument");
+    uint32_t A_ret, A_out;
+    if (walk_multipliers(p, q, &A_ret, &A_out)) return set_error(N2V_EINVAL, "n2v_autotune: bad p or q");
+    TuneLayout T;
+    const size_t need = tune_layout(n_walks, L, ws, ws_bytes, &T);
+    if (need > ws_bytes) return set_error(N2V_ENOMEM, "n2v_autotune: workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_sample_starts, dim3((n_walks + 255) / 256), dim3(256), 0, st, T.starts, n_walks, g->dg.n,
+                       0x5eedu);
+    N2V_HIP(hipGetLastError());
+
+    JobCtx c;
+    c.out = T.out;
+    c.cnt = nullptr;
+    c.checksum = nullptr;
+    c.wbase = 0;
+    c.L = L;
+    c.k0 = 0x1234567u;
+    c.k1 = 0;
+    c.A_ret = A_ret;
+    c.A_out = A_out;
+
+    hipEvent_t e0, e1;
+    N2V_HIP(hipEventCreate(&e0));
+    N2V_HIP(hipEventCreate(&e1));
+    auto run = [&](const n2v_exec_opts &o, double *ms) -> int {
+        Exec E;
+        make_exec(g, o, &E);
+        int rc = launch_one(E, c, T.starts, n_walks, o, g->device, st);  // warm-up
+        if (rc) return rc;
+        N2V_HIP(hipEventRecord(e0, st));
+        rc = launch_one(E, c, T.starts, n_walks, o, g->device, st);
+        if (rc) return rc;
+        N2V_HIP(hipEventRecord(e1, st));
+        N2V_HIP(hipEventSynchronize(e1));
+        float f = 0;
+        N2V_HIP(hipEventElapsedTime(&f, e0, e1));
+        *ms = f;
+        return N2V_OK;
+    };
+
+    n2v_exec_opts cur;
+    g->has_tuned = false;
+    n2v_exec_opts_default(g, &cur);
+    cur.mode = N2V_MODE_PERSISTENT;
+    double cur_ms = 0;
+    int rc = run(cur, &cur_ms);
+    if (rc) return rc;
+    const uint32_t t_wave_c[] = {0, 8, 32, 64, 128, 256, 1024};
+    const uint32_t ratio_c[] = {1, 2, 4, 8, 16};
+    const uint32_t waves_c[] = {0, 8, 12, 16};
+    for (int pass = 0; pass < 3; ++pass) {
+        const uint32_t *vals = pass == 0 ? t_wave_c : pass == 1 ? ratio_c : waves_c;
+        const int nv = pass == 0 ? 7 : pass == 1 ? 5 : 4;
+        for (int i = 0; i < nv; ++i) {
+            n2v_exec_opts o = cur;
+            if (pass == 0) o.t_wave = vals[i];
+            if (pass == 1) o.sparse_ratio = vals[i];
+            if (pass == 2) o.waves_per_cu = vals[i];
+            double ms = 0;
+            rc = run(o, &ms);
+            if (rc) return rc;
+            if (ms < cur_ms) {
+                cur = o;
+                cur_ms = ms;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cur.mode = N2V_MODE_AUTO;
+    g->tuned = cur;
+    g->has_tuned = true;
+    if (best) *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return N2V_OK;
+}

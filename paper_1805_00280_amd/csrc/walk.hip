@@ -1,0 +1,1012 @@
+// walk.hip -- node2vec second-order walk kernels.
+//
+// A move from v (previous vertex t) draws the next vertex x with probability
+// proportional to pi_x = w_vx * A(t, x), A = A_ret (x = t), A_com (x a
+// neighbour of t), A_out (otherwise): the model of Section 2.1 of the paper
+// with the probabilities computed on demand as in Section 3.2, never stored.
+// The first move uses the edge weights alone (Algorithm 1).
+//
+// Execution classes (all give bit-identical results; they only decide who
+// evaluates the rule):
+//   thread  -- one lane runs a rejection move of its own walk;
+//   wave    -- 64 lanes evaluate 64 rejection attempts at once and keep the
+//              lowest accepting attempt index;
+//   hub     -- a wavefront evaluates the inverse CDF of a high-degree vertex:
+//              it intersects N(v) with N(t), forms S = sum pi, draws
+//              r = hi64(R1, S) and finds the first prefix sum above r, by a
+//              chunked merge-intersection staged in LDS (dense) or by
+//              searching the members of a short N(t) in N(v) (sparse).
+//
+// Forms: PLAIN = one superstep per move (a thread kernel plus a hub kernel
+// with one workgroup per hub move, as a BSP superstep advances every walk by
+// one move); PERSISTENT = one launch, each wavefront owns 64 walk slots and
+// switches between thread and wave classes.
+#include <math.h>
+#include <stdlib.h>
+
+#include <algorithm>
+
+#include "prims.hpp"
+#include "walk.hpp"
+
+namespace n2v {
+
+constexpr uint32_t A_COM = 4;
+
+// Walk state carried from move to move.
+struct WS {
+    uint32_t job;    // job the walk belongs to
+    uint32_t i;      // index of the walk within its job (row of out)
+    uint32_t s;      // moves taken so far
+    uint32_t v, t;   // current and previous vertex
+    uint64_t vo;     // row offset of v
+    uint32_t vd, vw; // degree and largest weight of v
+    uint64_t to;     // row offset of t
+    uint32_t td;     // degree of t
+    uint32_t pos_t;  // index of t in N(v), SENT if absent
+    uint32_t jprev;  // index of v in N(t)
+};
+
+namespace {
+
+constexpr int HCH = 512;            // hub sub-chunk: 8 entries per lane
+constexpr int HEPL = HCH / WAVE;
+constexpr int NSUPER = 128;         // chunk sums held per wavefront
+constexpr int SPCAP = 512;          // specials held by the sparse path
+
+// LDS of one wavefront for hub moves (6 KiB).
+struct HubLds {
+    union {
+        struct {
+            uint32_t xs[HCH];
+            uint8_t flag[HCH];
+        } d;
+        struct {
+            uint32_t pos[SPCAP];
+            int32_t del[SPCAP];
+        } sp;
+    } a;
+    union {
+        struct {
+            uint64_t csum[NSUPER];
+            uint32_t cy[NSUPER];
+        } d;
+        int32_t dl[HCH];
+    } b;
+};
+
+__device__ __forceinline__ uint32_t amax3(const JobCtx &J)
+{
+    uint32_t m = J.A_ret > A_COM ? J.A_ret : A_COM;
+    return m > J.A_out ? m : J.A_out;
+}
+
+template <bool WALKS, bool COUNTS>
+__device__ __forceinline__ void emit(const JobCtx &J, uint32_t i, uint32_t col, uint32_t x, uint64_t &csum)
+{
+    if (WALKS) J.out[(uint64_t)i * (J.L + 1) + col] = x;
+    if (COUNTS) {
+        atomicAdd(&J.cnt[x], 1u);
+        const R4 h = philox(J.k0, J.k1, J.wbase + i, col, x, 3u);
+        csum += join64(h.x, h.y);
+    }
+}
+
+__device__ __forceinline__ void load_v(const Exec &E, WS &st, uint32_t x)
+{
+    const VRec r = E.g.vrec[x];
+    st.v = x;
+    st.vo = r.off;
+    st.vd = r.deg;
+    st.vw = r.wmax;
+}
+
+// Neighbour index j of v -> (x, position of v in N(x)).
+__device__ __forceinline__ void resolve(const Exec &E, const WS &st, uint32_t j, uint32_t &x, uint32_t &rev)
+{
+    if (st.s > 0 && j == st.pos_t) {
+        x = st.t;
+        rev = st.jprev;
+    } else {
+        const uint2 e = E.g.erec[st.vo + j];
+        x = e.x;
+        rev = e.y;
+    }
+}
+
+__device__ __forceinline__ void advance(const Exec &E, WS &st, uint32_t j, uint32_t x, uint32_t rev)
+{
+    st.t = st.v;
+    st.to = st.vo;
+    st.td = st.vd;
+    st.jprev = j;
+    st.pos_t = rev;
+    load_v(E, st, x);
+    st.s += 1;
+}
+
+// One rejection attempt k; returns whether it accepts and its neighbour index.
+__device__ __forceinline__ bool attempt(const Exec &E, const JobCtx &J, const WS &st, uint32_t k, uint32_t &j_out)
+{
+    const bool first = st.s == 0;
+    const uint64_t E_env = (uint64_t)st.vw * (first ? 1u : amax3(J));
+    const R4 r = philox(J.k0, J.k1, J.wbase + st.i, st.s, k, 0u);
+    const uint64_t j = hi64(join64(r.x, r.y), st.vd);
+    const uint64_t u = hi64(join64(r.z, r.w), E_env);
+    const uint64_t w = E.g.wt ? E.g.wt[st.vo + j] : 1u;
+    const uint32_t acmin = A_COM < J.A_out ? A_COM : J.A_out;
+    const uint32_t acmax = A_COM < J.A_out ? J.A_out : A_COM;
+    bool acc;
+    if (first) acc = u < w;
+    else if (j == st.pos_t) acc = u < J.A_ret * w;
+    else if (u < acmin * w) acc = true;
+    else if (u >= acmax * w) acc = false;
+    else {
+        const uint32_t x = E.g.adj[st.vo + j];
+        const bool com = contains_g(E.g.adj, st.to, st.to + st.td, x);
+        acc = u < (uint64_t)(com ? A_COM : J.A_out) * w;
+    }
+    j_out = (uint32_t)j;
+    return acc;
+}
+
+// Thread class: attempts in order until one accepts (false after a_cap).
+__device__ bool thread_reject(const Exec &E, const JobCtx &J, const WS &st, uint32_t &j_out)
+{
+    for (uint32_t k = 0; k < E.g.a_cap; ++k)
+        if (attempt(E, J, st, k, j_out)) return true;
+    return false;
+}
+
+// Wave class: lanes take attempts k0 + lane; the lowest accepting one wins.
+__device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st, uint32_t &j_out)
+{
+    const int l = lane_id();
+    for (uint32_t k0 = 0; k0 < E.g.a_cap; k0 += WAVE) {
+        const uint32_t k = k0 + l;
+        uint32_t j = 0;
+        const bool acc = k < E.g.a_cap && attempt(E, J, st, k, j);
+        const uint64_t m = ballot(acc);
+        if (m) {
+            j_out = shfl32(j, first_lane(m));
+            return true;
+        }
+    }
+    return false;
+}
+
+// ------------------------------------------------------------------ hubs
+// Stages N(v)[j0, j0+cnt) in LDS and flags the members of N(t), streaming
+// N(t) from ypos (advanced past every value <= the chunk's last entry).
+__device__ void dense_flags(const Exec &E, const WS &st, HubLds &L, uint64_t j0, uint32_t cnt, uint64_t &ypos)
+{
+    const int l = lane_id();
+    const uint32_t *__restrict__ adj = E.g.adj;
+#pragma unroll
+    for (int e = 0; e < HEPL; ++e) {
+        const uint32_t i = e * WAVE + l;
+        L.a.d.xs[i] = i < cnt ? adj[st.vo + j0 + i] : 0xFFFFFFFFu;
+        L.a.d.flag[i] = 0;
+    }
+    wave_lds_sync();
+    const uint32_t xlast = L.a.d.xs[cnt - 1];
+    const uint64_t td = st.td;
+    while (ypos < td) {
+        uint32_t y[4];
+        bool in[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint64_t idx = ypos + b * WAVE + l;
+            const bool valid = idx < td;
+            y[b] = valid ? adj[st.to + idx] : 0xFFFFFFFFu;
+            in[b] = valid && y[b] <= xlast;
+        }
+        uint32_t nin = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            nin += __popcll(ballot(in[b]));
+            if (in[b]) {
+                uint32_t lo = 0, hi = cnt;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (L.a.d.xs[mid] < y[b]) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo < cnt && L.a.d.xs[lo] == y[b]) L.a.d.flag[lo] = 1;
+            }
+        }
+        ypos += nin;
+        if (nin < 4 * WAVE) break;
+    }
+    wave_lds_sync();
+}
+
+__device__ __forceinline__ uint64_t dense_pi(const Exec &E, const JobCtx &J, const WS &st, const HubLds &L,
+                                             uint64_t j0, uint32_t i)
+{
+    const uint64_t w = E.g.wt ? E.g.wt[st.vo + j0 + i] : 1u;
+    const uint32_t m = (j0 + i == st.pos_t) ? J.A_ret : (L.a.d.flag[i] ? A_COM : J.A_out);
+    return w * m;
+}
+
+__device__ uint64_t dense_chunk_sum(const Exec &E, const JobCtx &J, const WS &st, const HubLds &L, uint64_t j0,
+                                    uint32_t cnt)
+{
+    const int l = lane_id();
+    uint64_t s = 0;
+#pragma unroll
+    for (int e = 0; e < HEPL; ++e) {
+        const uint32_t i = e * WAVE + l;
+        if (i < cnt) s += dense_pi(E, J, st, L, j0, i);
+    }
+    return wave_sum(s);
+}
+
+// First index of the chunk whose running prefix (base + partial) exceeds r,
+// or SENT (base then holds the prefix after the chunk).
+__device__ uint32_t dense_chunk_locate(const Exec &E, const JobCtx &J, const WS &st, const HubLds &L, uint64_t j0,
+                                       uint32_t cnt, uint64_t &base, uint64_t r)
+{
+    const int l = lane_id();
+#pragma unroll 1
+    for (int e = 0; e < HEPL; ++e) {
+        const uint32_t i = e * WAVE + l;
+        const uint64_t pi = i < cnt ? dense_pi(E, J, st, L, j0, i) : 0;
+        const uint64_t inc = wave_incl_scan(pi);
+        const uint64_t m = ballot(i < cnt && base + inc > r);
+        if (m) return (uint32_t)(j0 + e * WAVE + first_lane(m));
+        base += shfl64(inc, WAVE - 1);
+    }
+    return SENT;
+}
+
+// Dense inverse CDF of a second-order move over all of N(v).
+__device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, uint64_t R1)
+{
+    const int l = lane_id();
+    const uint64_t dv = st.vd;
+    const uint64_t nsub = (dv + HCH - 1) / HCH;
+    const uint64_t G = (nsub + NSUPER - 1) / NSUPER;
+    const uint64_t nsup = (nsub + G - 1) / G;
+    uint64_t ypos = 0;
+    if (st.td) ypos = lower_bound_g(E.g.adj, st.to, st.to + st.td, E.g.adj[st.vo]) - st.to;
+    uint64_t S = 0;
+    for (uint64_t sp = 0; sp < nsup; ++sp) {
+        const uint64_t y0 = ypos;
+        uint64_t sum = 0;
+        const uint64_t sub_end = std::min(nsub, (sp + 1) * G);
+        for (uint64_t sub = sp * G; sub < sub_end; ++sub) {
+            const uint64_t j0 = sub * HCH;
+            const uint32_t cnt = (uint32_t)std::min<uint64_t>(HCH, dv - j0);
+            dense_flags(E, st, L, j0, cnt, ypos);
+            sum += dense_chunk_sum(E, J, st, L, j0, cnt);
+            wave_lds_sync();
+        }
+        if (l == 0) {
+            L.b.d.csum[sp] = sum;
+            L.b.d.cy[sp] = (uint32_t)y0;
+        }
+        S += sum;
+    }
+    wave_lds_sync();
+    const uint64_t r = hi64(R1, S);
+    uint64_t base = 0, spx = nsup - 1;
+    for (uint64_t b0 = 0; b0 < nsup; b0 += WAVE) {
+        const uint64_t idx = b0 + l;
+        const uint64_t c = idx < nsup ? L.b.d.csum[idx] : 0;
+        const uint64_t inc = wave_incl_scan(c);
+        const uint64_t m = ballot(idx < nsup && base + inc > r);
+        if (m) {
+            const int f = first_lane(m);
+            spx = b0 + f;
+            base += shfl64(inc - c, f);
+            break;
+        }
+        base += shfl64(inc, WAVE - 1);
+    }
+    ypos = L.b.d.cy[spx];
+    wave_lds_sync();
+    const uint64_t sub_end = std::min(nsub, (spx + 1) * G);
+    for (uint64_t sub = spx * G; sub < sub_end; ++sub) {
+        const uint64_t j0 = sub * HCH;
+        const uint32_t cnt = (uint32_t)std::min<uint64_t>(HCH, dv - j0);
+        dense_flags(E, st, L, j0, cnt, ypos);
+        const uint32_t j = dense_chunk_locate(E, J, st, L, j0, cnt, base, r);
+        wave_lds_sync();
+        if (j != SENT) return j;
+    }
+    return (uint32_t)(dv - 1);  // not reached: the last prefix equals S > r
+}
+
+// Weighted scan with specials: pi_j = m0 * w_j + delta_j, the deltas of the
+// c specials (sorted positions, in LDS) scattered chunk by chunk.
+__device__ uint32_t weighted_scan_locate(const Exec &E, const WS &st, HubLds &L, uint32_t m0, uint32_t c, uint64_t r)
+{
+    const int l = lane_id();
+    const uint64_t dv = st.vd;
+    uint64_t base = 0;
+    uint32_t kp = 0;
+    for (uint64_t j0 = 0; j0 < dv; j0 += HCH) {
+        const uint32_t cnt = (uint32_t)std::min<uint64_t>(HCH, dv - j0);
+#pragma unroll
+        for (int e = 0; e < HEPL; ++e) L.b.dl[e * WAVE + l] = 0;
+        wave_lds_sync();
+        while (kp < c) {
+            const uint32_t k = kp + l;
+            const bool in = k < c && L.a.sp.pos[k] < j0 + cnt;
+            if (in) L.b.dl[L.a.sp.pos[k] - j0] = L.a.sp.del[k];
+            const uint32_t n_in = __popcll(ballot(in));
+            kp += n_in;
+            if (n_in < WAVE) break;
+        }
+        wave_lds_sync();
+#pragma unroll 1
+        for (int e = 0; e < HEPL; ++e) {
+            const uint32_t i = e * WAVE + l;
+            uint64_t pi = 0;
+            if (i < cnt) pi = (uint64_t)((int64_t)m0 * E.g.wt[st.vo + j0 + i] + L.b.dl[i]);
+            const uint64_t inc = wave_incl_scan(pi);
+            const uint64_t m = ballot(i < cnt && base + inc > r);
+            if (m) {
+                wave_lds_sync();
+                return (uint32_t)(j0 + e * WAVE + first_lane(m));
+            }
+            base += shfl64(inc, WAVE - 1);
+        }
+        wave_lds_sync();
+    }
+    return (uint32_t)(dv - 1);  // not reached
+}
+
+// Sparse inverse CDF: the members of N(t) are searched in N(v); they and t
+// are the only entries whose multiplier differs from A_out.
+__device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, uint64_t R1)
+{
+    const int l = lane_id();
+    const uint32_t *__restrict__ adj = E.g.adj;
+    const uint64_t vo = st.vo, dv = st.vd;
+    uint32_t c = 0;
+    for (uint32_t b = 0; b < st.td; b += WAVE) {
+        const uint32_t idx = b + l;
+        const bool valid = idx < st.td;
+        bool found = false;
+        uint64_t p = 0;
+        if (valid) {
+            const uint32_t y = adj[st.to + idx];
+            p = lower_bound_g(adj, vo, vo + dv, y);
+            found = p < vo + dv && adj[p] == y;
+        }
+        const uint64_t m = ballot(found);
+        if (found) L.a.sp.pos[c + __popcll(m & lanemask_lt())] = (uint32_t)(p - vo);
+        c += __popcll(m);
+    }
+    wave_lds_sync();
+    // insert t's own position (t is never a member of N(t))
+    if (st.pos_t != SENT) {
+        uint32_t vals[SPCAP / WAVE];
+        uint32_t nless = 0;
+#pragma unroll
+        for (int e = 0; e < SPCAP / WAVE; ++e) {
+            const uint32_t k = e * WAVE + l;
+            vals[e] = k < c ? L.a.sp.pos[k] : SENT;
+            nless += (k < c && vals[e] < st.pos_t);
+        }
+        nless = wave_sum32(nless);
+        wave_lds_sync();
+#pragma unroll
+        for (int e = 0; e < SPCAP / WAVE; ++e) {
+            const uint32_t k = e * WAVE + l;
+            if (k < c) L.a.sp.pos[k + (vals[e] > st.pos_t ? 1u : 0u)] = vals[e];
+        }
+        if (l == 0) L.a.sp.pos[nless] = st.pos_t;
+        c += 1;
+        wave_lds_sync();
+    }
+    // deltas pi_j - A_out * w_j and their sum
+    int64_t dsum = 0;
+    for (uint32_t k = l; k < c; k += WAVE) {
+        const uint32_t p = L.a.sp.pos[k];
+        const int64_t w = E.g.wt ? E.g.wt[vo + p] : 1;
+        const int64_t mult = (p == st.pos_t) ? (int64_t)J.A_ret : (int64_t)A_COM;
+        const int32_t dl = (int32_t)((mult - (int64_t)J.A_out) * w);
+        L.a.sp.del[k] = dl;
+        dsum += dl;
+    }
+    dsum = (int64_t)wave_sum((uint64_t)dsum);
+    wave_lds_sync();
+    const uint64_t W = E.g.wt ? E.g.wsum[st.v] : dv;
+    const uint64_t S = (uint64_t)((int64_t)(J.A_out * W) + dsum);
+    const uint64_t r = hi64(R1, S);
+    if (E.g.wt) return weighted_scan_locate(E, st, L, J.A_out, c, r);
+    // unweighted: between specials the prefix grows by A_out per entry
+    int64_t D = 0;       // deltas of the specials before this block
+    int64_t qprev = -1;  // position of the special before this block
+    for (uint32_t b = 0; b < c; b += WAVE) {
+        const uint32_t k = b + l;
+        const bool valid = k < c;
+        const int64_t q = valid ? (int64_t)L.a.sp.pos[k] : 0;
+        const int64_t dl = valid ? (int64_t)L.a.sp.del[k] : 0;
+        const int64_t inc = (int64_t)wave_incl_scan((uint64_t)dl);
+        const int64_t Dincl = D + inc;
+        const bool cross = valid && (int64_t)J.A_out * (q + 1) + Dincl > (int64_t)r;
+        const uint64_t m = ballot(cross);
+        const int64_t qleft = (int64_t)shfl64((uint64_t)q, l > 0 ? l - 1 : 0);
+        if (m) {
+            const int f = first_lane(m);
+            const int64_t qf = (int64_t)shfl64((uint64_t)q, f);
+            const int64_t Dexcl = (int64_t)shfl64((uint64_t)(Dincl - dl), f);
+            const int64_t qlf = (int64_t)shfl64((uint64_t)qleft, f);
+            const int64_t qp = f > 0 ? qlf : qprev;
+            int64_t ig = ((int64_t)r - Dexcl) / (int64_t)J.A_out;
+            if (ig < qp + 1) ig = qp + 1;
+            return (uint32_t)(ig < qf ? ig : qf);
+        }
+        D += (int64_t)shfl64((uint64_t)inc, WAVE - 1);
+        const uint32_t last = c - 1 - b < (uint32_t)(WAVE - 1) ? c - 1 - b : (uint32_t)(WAVE - 1);
+        qprev = (int64_t)shfl64((uint64_t)q, (int)last);
+    }
+    int64_t ig = ((int64_t)r - D) / (int64_t)J.A_out;
+    if (ig < qprev + 1) ig = qprev + 1;
+    return (uint32_t)ig;
+}
+
+__device__ __forceinline__ bool use_sparse(const Exec &E, const WS &st)
+{
+    if (st.td + 1 > (uint32_t)SPCAP || st.td > E.t_sparse) return false;
+    const uint32_t lg = 32 - __clz(st.vd);
+    return (uint64_t)st.td * E.sparse_ratio * lg < (uint64_t)st.vd + st.td;
+}
+
+// Inverse CDF of one move by a wavefront (state uniform across lanes).
+__device__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &st, uint32_t kidx, HubLds &L)
+{
+    const R4 rr = philox(J.k0, J.k1, J.wbase + st.i, st.s, kidx, 0u);
+    const uint64_t R1 = join64(rr.x, rr.y);
+    if (st.s == 0) {
+        if (!E.g.wt) return (uint32_t)hi64(R1, st.vd);
+        return weighted_scan_locate(E, st, L, 1u, 0u, hi64(R1, E.g.wsum[st.v]));
+    }
+    uint32_t j = use_sparse(E, st) ? hub_sparse(E, J, st, L, R1) : hub_dense(E, J, st, L, R1);
+    if (j >= st.vd) {  // cannot happen for a correct rule; keeps every read inside the row
+        if (lane_id() == 0) atomicOr(E.g.status, 2u);
+        j = st.vd - 1;
+    }
+    return j;
+}
+
+__device__ WS bcast(const WS &s, int o)
+{
+    WS w;
+    w.job = shfl32(s.job, o);
+    w.i = shfl32(s.i, o);
+    w.s = shfl32(s.s, o);
+    w.v = shfl32(s.v, o);
+    w.t = shfl32(s.t, o);
+    w.vo = shfl64(s.vo, o);
+    w.vd = shfl32(s.vd, o);
+    w.vw = shfl32(s.vw, o);
+    w.to = shfl64(s.to, o);
+    w.td = shfl32(s.td, o);
+    w.pos_t = shfl32(s.pos_t, o);
+    w.jprev = shfl32(s.jprev, o);
+    return w;
+}
+
+template <bool WALKS>
+__device__ __forceinline__ void fill_tail_lane(const JobCtx &J, uint32_t i, uint32_t s)
+{
+    if (WALKS)
+        for (uint32_t c = s + 1; c <= J.L; ++c) J.out[(uint64_t)i * (J.L + 1) + c] = SENT;
+}
+
+template <bool WALKS>
+__device__ __forceinline__ void fill_tail_wave(const JobCtx &J, uint32_t i, uint32_t s)
+{
+    if (WALKS)
+        for (uint32_t c = s + 1 + lane_id(); c <= J.L; c += WAVE) J.out[(uint64_t)i * (J.L + 1) + c] = SENT;
+}
+
+// Starts walk i of a job in lane state st; returns whether it has a move to make.
+template <bool WALKS, bool COUNTS>
+__device__ bool start_walk(const Exec &E, const JobCtx &J, uint32_t job, uint32_t i, uint32_t x, WS &st,
+                           uint64_t &csum)
+{
+    st.job = job;
+    st.i = i;
+    st.s = 0;
+    st.t = SENT;
+    st.to = 0;
+    st.td = 0;
+    st.pos_t = SENT;
+    st.jprev = SENT;
+    if (x >= E.g.n) {
+        atomicOr(E.g.status, 1u);
+        if (WALKS) J.out[(uint64_t)i * (J.L + 1)] = x;
+        fill_tail_lane<WALKS>(J, i, 0);
+        return false;
+    }
+    emit<WALKS, COUNTS>(J, i, 0, x, csum);
+    load_v(E, st, x);
+    if (st.vd == 0) {
+        fill_tail_lane<WALKS>(J, i, 0);
+        return false;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------- job sources
+// One job for the whole launch (kernel arguments, uniform).
+struct OneJob {
+    JobCtx c;
+    const uint32_t *starts;
+    uint32_t n;
+    __device__ uint32_t total() const { return n; }
+    __device__ void locate(uint32_t g, uint32_t &job, uint32_t &i) const
+    {
+        job = 0;
+        i = g;
+    }
+    __device__ JobCtx ctx(uint32_t) const { return c; }
+    __device__ uint32_t start(uint32_t, uint32_t i) const { return starts[i]; }
+};
+
+// A table of jobs (serving): walk g belongs to the job whose prefix range
+// holds it.  The header (job count, walk count) lives in device memory so that
+// one captured launch can be replayed over tables of any content.
+struct JobTable {
+    const TableHdr *hdr;
+    __device__ uint32_t total() const { return hdr->total; }
+    __device__ void locate(uint32_t g, uint32_t &job, uint32_t &i) const
+    {
+        uint32_t lo = 0, hi = hdr->njobs;  // last job with jstart <= g
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (hdr->jstart[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        job = lo;
+        i = g - hdr->jstart[lo];
+    }
+    __device__ JobCtx ctx(uint32_t job) const { return hdr->jobs[job].c; }
+    __device__ uint32_t start(uint32_t job, uint32_t i) const { return hdr->jobs[job].starts[i]; }
+};
+
+// ---------------------------------------------------------- persistent
+constexpr int PBLOCK = 256;
+constexpr int THREAD_ITERS = 8;
+
+template <class Src, bool WALKS, bool COUNTS>
+__global__ __launch_bounds__(PBLOCK) void k_persistent(Exec E, Src S)
+{
+    __shared__ HubLds lds[PBLOCK / WAVE];
+    HubLds &L = lds[threadIdx.x / WAVE];
+    const int l = lane_id();
+    const uint64_t gw = (uint64_t)blockIdx.x * (PBLOCK / WAVE) + threadIdx.x / WAVE;
+    const uint64_t stride = (uint64_t)gridDim.x * PBLOCK;
+    const uint32_t total = S.total();
+    uint64_t next = gw * WAVE + l;
+    WS st{};
+    bool live = false, pend = false;
+    uint32_t pk = 0;
+    uint64_t csum = 0;
+    const uint32_t tw = E.t_wave < E.g.d_rule ? E.t_wave : E.g.d_rule;
+    for (;;) {
+        while (!live && next < total) {
+            uint32_t job, i;
+            S.locate((uint32_t)next, job, i);
+            const JobCtx J = S.ctx(job);
+            live = start_walk<WALKS, COUNTS>(E, J, job, i, S.start(job, i), st, csum);
+            pend = false;
+            next += stride;
+        }
+        if (ballot(live) == 0) break;
+        // thread class
+        for (int it = 0; it < THREAD_ITERS; ++it) {
+            if (live && !pend && st.vd > tw) {
+                pend = true;
+                pk = 0;
+            }
+            const bool can = live && !pend;
+            if (ballot(can) == 0) break;
+            if (can) {
+                const JobCtx J = S.ctx(st.job);
+                uint32_t j;
+                if (thread_reject(E, J, st, j)) {
+                    uint32_t x, rev;
+                    resolve(E, st, j, x, rev);
+                    emit<WALKS, COUNTS>(J, st.i, st.s + 1, x, csum);
+                    advance(E, st, j, x, rev);
+                    if (st.s == J.L || st.vd == 0) {
+                        fill_tail_lane<WALKS>(J, st.i, st.s);
+                        live = false;
+                    }
+                } else {
+                    pend = true;
+                    pk = E.g.a_cap;
+                }
+            }
+        }
+        if (live && !pend) {
+            pend = st.vd > tw;
+            pk = 0;
+        }
+        // wave and hub classes, one pending walk at a time
+        uint64_t pm = ballot(live && pend);
+        while (pm) {
+            const int o = first_lane(pm);
+            pm &= pm - 1;
+            WS w = bcast(st, o);
+            w.job = __builtin_amdgcn_readfirstlane(w.job);
+            const JobCtx J = S.ctx(w.job);
+            uint32_t k = shfl32(pk, o);
+            bool alive = true;
+            for (;;) {
+                uint32_t j;
+                if (k == E.g.a_cap) j = wave_inverse_cdf(E, J, w, k, L);
+                else if (w.vd > E.g.d_rule) j = wave_inverse_cdf(E, J, w, 0, L);
+                else if (!wave_reject(E, J, w, j)) j = wave_inverse_cdf(E, J, w, E.g.a_cap, L);
+                uint32_t x, rev;
+                resolve(E, w, j, x, rev);
+                if (l == 0) emit<WALKS, COUNTS>(J, w.i, w.s + 1, x, csum);
+                advance(E, w, j, x, rev);
+                k = 0;
+                if (w.s == J.L || w.vd == 0) {
+                    fill_tail_wave<WALKS>(J, w.i, w.s);
+                    alive = false;
+                    break;
+                }
+                if (w.vd <= tw) break;
+            }
+            if (l == o) {
+                st = w;
+                live = alive;
+                pend = false;
+            }
+        }
+    }
+    if (COUNTS) {
+        csum = wave_sum(csum);
+        if (l == 0 && csum) atomicAdd(S.ctx(0).checksum, (unsigned long long)csum);
+    }
+}
+
+// --------------------------------------------------------------- plain
+// Per-walk state between supersteps: (v, t, pos_t, jprev); v = SENT once done.
+template <bool WALKS, bool COUNTS>
+__global__ __launch_bounds__(256) void k_plain_init(Exec E, OneJob S, uint4 *__restrict__ state)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t csum = 0;
+    if (i < S.n) {
+        WS st;
+        const bool live = start_walk<WALKS, COUNTS>(E, S.c, 0, i, S.starts[i], st, csum);
+        state[i] = make_uint4(live ? st.v : SENT, SENT, SENT, SENT);
+    }
+    if (COUNTS) {
+        csum = wave_sum(csum);
+        if (lane_id() == 0 && csum) atomicAdd(S.c.checksum, (unsigned long long)csum);
+    }
+}
+
+__device__ __forceinline__ bool plain_load(const Exec &E, const uint4 &q, uint32_t i, uint32_t s, WS &st)
+{
+    if (q.x == SENT) return false;
+    st.job = 0;
+    st.i = i;
+    st.s = s;
+    load_v(E, st, q.x);
+    st.t = q.y;
+    st.pos_t = q.z;
+    st.jprev = q.w;
+    if (s > 0) {
+        const VRec r = E.g.vrec[q.y];
+        st.to = r.off;
+        st.td = r.deg;
+    } else {
+        st.to = 0;
+        st.td = 0;
+    }
+    return true;
+}
+
+template <bool WALKS, bool COUNTS>
+__device__ __forceinline__ void plain_finish(const Exec &E, const JobCtx &J, WS &st, uint32_t j, uint4 *state,
+                                             uint64_t &csum, bool wave)
+{
+    uint32_t x, rev;
+    resolve(E, st, j, x, rev);
+    if (!wave || lane_id() == 0) emit<WALKS, COUNTS>(J, st.i, st.s + 1, x, csum);
+    const uint32_t s1 = st.s + 1;
+    bool end = s1 == J.L;
+    if (!end) {
+        const VRec r = E.g.vrec[x];
+        if (r.deg == 0) {
+            end = true;
+            if (wave) fill_tail_wave<WALKS>(J, st.i, s1);
+            else fill_tail_lane<WALKS>(J, st.i, s1);
+        }
+    }
+    if (!wave || lane_id() == 0) state[st.i] = make_uint4(end ? SENT : x, st.v, rev, j);
+}
+
+template <bool WALKS, bool COUNTS>
+__global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
+                                                    uint32_t *__restrict__ hubq, uint32_t *__restrict__ hubn)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t csum = 0;
+    bool push = false;
+    uint32_t item = 0;
+    if (i < S.n) {
+        WS st;
+        if (plain_load(E, state[i], i, s, st)) {
+            if (st.vd > E.g.d_rule) {
+                push = true;
+                item = i;
+            } else {
+                uint32_t j;
+                if (thread_reject(E, S.c, st, j)) plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, false);
+                else {
+                    push = true;
+                    item = i | 0x80000000u;
+                }
+            }
+        }
+    }
+    const uint64_t m = ballot(push);
+    if (m) {
+        uint32_t base = 0;
+        const int lead = first_lane(m);
+        if (lane_id() == lead) base = atomicAdd(hubn, (uint32_t)__popcll(m));
+        base = shfl32(base, lead);
+        if (push) hubq[base + __popcll(m & lanemask_lt())] = item;
+    }
+    if (COUNTS) {
+        csum = wave_sum(csum);
+        if (lane_id() == 0 && csum) atomicAdd(S.c.checksum, (unsigned long long)csum);
+    }
+}
+
+// One workgroup-resident wavefront per hub move of this superstep.
+template <bool WALKS, bool COUNTS>
+__global__ __launch_bounds__(256) void k_plain_hub(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
+                                                   const uint32_t *__restrict__ hubq, const uint32_t *__restrict__ hubn)
+{
+    __shared__ HubLds lds[256 / WAVE];
+    HubLds &L = lds[threadIdx.x / WAVE];
+    const uint32_t gw = blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    const uint32_t nw = gridDim.x * (256 / WAVE);
+    const uint32_t n = *hubn;
+    uint64_t csum = 0;
+    for (uint32_t q = gw; q < n; q += nw) {
+        const uint32_t item = hubq[q];
+        const uint32_t i = item & 0x7FFFFFFFu;
+        const uint32_t kidx = (item & 0x80000000u) ? E.g.a_cap : 0u;
+        WS st;
+        plain_load(E, state[i], i, s, st);
+        const uint32_t j = wave_inverse_cdf(E, S.c, st, kidx, L);
+        plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, true);
+    }
+    if (COUNTS) {
+        csum = wave_sum(csum);
+        if (lane_id() == 0 && csum) atomicAdd(S.c.checksum, (unsigned long long)csum);
+    }
+}
+
+__global__ void k_zero(uint32_t *p, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// ---------------------------------------------------------------- host
+struct DevInfo {
+    int cus = 0;
+    int occ = 0;
+};
+
+DevInfo &dev_info(int dev)
+{
+    static DevInfo info[64];
+    DevInfo &d = info[dev & 63];
+    if (d.cus == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) d.cus = prop.multiProcessorCount;
+        if (d.cus <= 0) d.cus = 256;
+        int b = 0;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)k_persistent<OneJob, true, true>,
+                                                           PBLOCK, 0);
+        d.occ = b > 0 ? b : 2;
+    }
+    return d;
+}
+
+size_t plain_ws(uint32_t n_starts, uint32_t L)
+{
+    Carver c(nullptr, 0);
+    c.take<uint4>(n_starts ? n_starts : 1);
+    c.take<uint32_t>(n_starts ? n_starts : 1);
+    c.take<uint32_t>((uint64_t)L + 1);
+    return c.total();
+}
+
+uint32_t persistent_blocks(const n2v_exec_opts &o, int dev, uint64_t walks)
+{
+    DevInfo &d = dev_info(dev);
+    uint32_t per_cu = o.waves_per_cu ? (o.waves_per_cu + (PBLOCK / WAVE) - 1) / (PBLOCK / WAVE) : (uint32_t)d.occ;
+    if (per_cu > (uint32_t)d.occ) per_cu = d.occ;
+    if (per_cu < 1) per_cu = 1;
+    uint64_t blocks = (uint64_t)d.cus * per_cu;
+    const uint64_t need = (walks + PBLOCK - 1) / PBLOCK;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    return (uint32_t)blocks;
+}
+
+template <bool W, bool C>
+int launch_persistent(const Exec &E, const OneJob &S, const n2v_exec_opts &o, int dev, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_persistent<OneJob, W, C>), dim3(persistent_blocks(o, dev, S.n)), dim3(PBLOCK), 0, st, E, S);
+    N2V_HIP(hipGetLastError());
+    return N2V_OK;
+}
+
+template <bool W, bool C>
+int launch_plain(const Exec &E, const OneJob &S, void *ws, int dev, hipStream_t st)
+{
+    Carver c(ws, (size_t)-1);
+    uint4 *state = c.take<uint4>(S.n ? S.n : 1);
+    uint32_t *hubq = c.take<uint32_t>(S.n ? S.n : 1);
+    uint32_t *hubn = c.take<uint32_t>((uint64_t)S.c.L + 1);
+    const uint32_t blocks = (S.n + 255) / 256;
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, hubn, S.c.L + 1);
+    hipLaunchKernelGGL((k_plain_init<W, C>), dim3(blocks), dim3(256), 0, st, E, S, state);
+    N2V_HIP(hipGetLastError());
+    DevInfo &d = dev_info(dev);
+    const uint32_t hub_blocks = (uint32_t)d.cus * 8;
+    for (uint32_t s = 0; s < S.c.L; ++s) {
+        hipLaunchKernelGGL((k_plain_step<W, C>), dim3(blocks), dim3(256), 0, st, E, S, s, state, hubq, hubn + s);
+        hipLaunchKernelGGL((k_plain_hub<W, C>), dim3(hub_blocks), dim3(256), 0, st, E, S, s, state, hubq,
+                           (const uint32_t *)(hubn + s));
+    }
+    N2V_HIP(hipGetLastError());
+    return N2V_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------- shared with other files
+int walk_multipliers(float p, float q, uint32_t *A_ret, uint32_t *A_out)
+{
+    static const float allowed[5] = {0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
+    static const uint32_t mult[5] = {16, 8, 4, 2, 1};
+    int ip = -1, iq = -1;
+    for (int i = 0; i < 5; ++i) {
+        if (p == allowed[i]) ip = i;
+        if (q == allowed[i]) iq = i;
+    }
+    if (ip < 0 || iq < 0) return -1;
+    *A_ret = mult[ip];
+    *A_out = mult[iq];
+    return 0;
+}
+
+void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E)
+{
+    E->g = g->dg;
+    E->t_wave = o.t_wave;
+    E->t_sparse = o.t_sparse;
+    E->sparse_ratio = o.sparse_ratio < 1 ? 1 : o.sparse_ratio;
+}
+
+uint32_t full_grid_blocks(int dev)
+{
+    DevInfo &d = dev_info(dev);
+    return (uint32_t)d.cus * (uint32_t)d.occ;
+}
+
+int launch_job_table(const Exec &E, const TableHdr *hdr, uint32_t blocks, hipStream_t st)
+{
+    JobTable T;
+    T.hdr = hdr;
+    hipLaunchKernelGGL((k_persistent<JobTable, true, false>), dim3(blocks), dim3(PBLOCK), 0, st, E, T);
+    N2V_HIP(hipGetLastError());
+    return N2V_OK;
+}
+
+int launch_one(const Exec &E, const JobCtx &c, const uint32_t *starts, uint32_t n, const n2v_exec_opts &o, int dev,
+               hipStream_t st)
+{
+    OneJob S;
+    S.c = c;
+    S.starts = starts;
+    S.n = n;
+    return launch_persistent<true, false>(E, S, o, dev, st);
+}
+
+}  // namespace n2v
+
+using namespace n2v;
+
+extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
+{
+    if (!o) return;
+    if (g && g->has_tuned) {
+        *o = g->tuned;
+        return;
+    }
+    o->mode = N2V_MODE_AUTO;
+    o->t_wave = 64;
+    o->t_sparse = 511;
+    o->sparse_ratio = 2;
+    o->waves_per_cu = 0;
+    o->block = 256;
+}
+
+extern "C" int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_t L, const n2v_exec_opts *opts,
+                                  size_t *ws_bytes)
+{
+    if (!g || !ws_bytes) return set_error(N2V_EINVAL, "n2v_walk_workspace: null argument");
+    n2v_exec_opts o;
+    n2v_exec_opts_default(g, &o);
+    if (opts) o = *opts;
+    *ws_bytes = o.mode == N2V_MODE_PLAIN ? plain_ws(n_starts, L) : 0;
+    return N2V_OK;
+}
+
+extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
+                           uint32_t L, float p, float q, uint64_t seed, const n2v_exec_opts *opts, int outputs,
+                           uint32_t *out, uint32_t *cnt, uint64_t *checksum, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!g) return set_error(N2V_EINVAL, "n2v_walk: null graph");
+    if (L < 1) return set_error(N2V_EINVAL, "n2v_walk: L must be >= 1");
+    uint32_t A_ret, A_out;
+    if (walk_multipliers(p, q, &A_ret, &A_out))
+        return set_error(N2V_EINVAL, "n2v_walk: p and q must be in {0.25, 0.5, 1, 2, 4}");
+    if (!(outputs & (N2V_OUT_WALKS | N2V_OUT_COUNTS)) || (outputs & ~(N2V_OUT_WALKS | N2V_OUT_COUNTS)))
+        return set_error(N2V_EINVAL, "n2v_walk: outputs must be a nonempty mask of N2V_OUT_WALKS | N2V_OUT_COUNTS");
+    const bool W = outputs & N2V_OUT_WALKS, C = outputs & N2V_OUT_COUNTS;
+    if (W && !out) return set_error(N2V_EINVAL, "n2v_walk: null out");
+    if (C && (!cnt || !checksum)) return set_error(N2V_EINVAL, "n2v_walk: null cnt or checksum");
+    if (walk_base + (uint64_t)n_starts > (1ull << 32)) return set_error(N2V_EINVAL, "n2v_walk: walk ids exceed 2^32");
+    if (n_starts >= 0x80000000u) return set_error(N2V_EINVAL, "n2v_walk: at most 2^31-1 walks per call");
+    if (n_starts == 0) return N2V_OK;
+    if (!starts) return set_error(N2V_EINVAL, "n2v_walk: null starts");
+    n2v_exec_opts o;
+    n2v_exec_opts_default(g, &o);
+    if (opts) o = *opts;
+
+    Exec E;
+    make_exec(g, o, &E);
+    OneJob S;
+    S.c.out = W ? out : nullptr;
+    S.c.cnt = C ? cnt : nullptr;
+    S.c.checksum = C ? (unsigned long long *)checksum : nullptr;
+    S.c.wbase = (uint32_t)walk_base;
+    S.c.L = L;
+    S.c.k0 = (uint32_t)seed;
+    S.c.k1 = (uint32_t)(seed >> 32);
+    S.c.A_ret = A_ret;
+    S.c.A_out = A_out;
+    S.starts = starts;
+    S.n = n_starts;
+    hipStream_t st = (hipStream_t)stream;
+
+    if (o.mode == N2V_MODE_PLAIN) {
+        const size_t need = plain_ws(n_starts, L);
+        if (!ws || ws_bytes < need) return set_error(N2V_ENOMEM, "n2v_walk: plain form needs %zu workspace bytes", need);
+        if (((uintptr_t)ws & 255) != 0) return set_error(N2V_EINVAL, "n2v_walk: workspace not 256-byte aligned");
+        if (W && C) return launch_plain<true, true>(E, S, ws, g->device, st);
+        if (W) return launch_plain<true, false>(E, S, ws, g->device, st);
+        return launch_plain<false, true>(E, S, ws, g->device, st);
+    }
+    if (W && C) return launch_persistent<true, true>(E, S, o, g->device, st);
+    if (W) return launch_persistent<true, false>(E, S, o, g->device, st);
+    return launch_persistent<false, true>(E, S, o, g->device, st);
+}
+
+extern "C" int n2v_walk(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint32_t L, float p, float q,
+                        uint64_t seed, uint32_t *out, void *stream)
+{
+    return n2v_walk_ex(g, starts, n_starts, 0, L, p, q, seed, nullptr, N2V_OUT_WALKS, out, nullptr, nullptr, nullptr,
+                       0, stream);
+}

@@ -1,0 +1,54 @@
+// walk.hpp -- parameter blocks of the walk kernels and the entry points the
+// autotuner and the server use.
+#pragma once
+
+#include "common.hpp"
+
+namespace n2v {
+
+// Graph view and execution parameters shared by every walk of a launch.
+// Execution parameters never change results.
+struct Exec {
+    DevGraph g;
+    uint32_t t_wave;        // rejection moves at degree > t_wave run wave-cooperatively
+    uint32_t t_sparse;      // largest deg(t) for the sparse hub path
+    uint32_t sparse_ratio;  // cost weight of one search against streaming
+};
+
+// Parameters of one walk job: a set of walks with the same (L, p, q, seed).
+// The common-neighbour multiplier is the constant K = 4.
+struct JobCtx {
+    uint32_t *out;                 // n x (L+1) rows or null
+    uint32_t *cnt;                 // visit counts or null
+    unsigned long long *checksum;  // or null
+    uint32_t wbase;                // walk id of the job's walk 0, modulo 2^32
+    uint32_t L;
+    uint32_t k0, k1;               // Philox key = seed
+    uint32_t A_ret, A_out;         // 4/p and 4/q
+};
+
+// One job of a serving table: its context plus its start ids.
+struct alignas(16) JobRec {
+    JobCtx c;
+    const uint32_t *starts;
+    uint32_t n;
+};
+
+constexpr uint32_t MAX_TABLE_JOBS = 256;
+
+// A table of jobs as the persistent kernel reads it from device memory.
+struct alignas(256) TableHdr {
+    uint32_t njobs;
+    uint32_t total;                         // sum of the job sizes
+    uint32_t jstart[MAX_TABLE_JOBS + 1];    // prefix sums of the job sizes
+    JobRec jobs[MAX_TABLE_JOBS];
+};
+
+int walk_multipliers(float p, float q, uint32_t *A_ret, uint32_t *A_out);
+void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E);
+uint32_t full_grid_blocks(int dev);
+int launch_job_table(const Exec &E, const TableHdr *hdr, uint32_t blocks, hipStream_t st);
+int launch_one(const Exec &E, const JobCtx &c, const uint32_t *starts, uint32_t n, const n2v_exec_opts &o, int dev,
+               hipStream_t st);
+
+}  // namespace n2v

@@ -20,3 +20,8 @@ def _oracle_built():
     if not os.path.exists(oracle.LIB_PATH):
         ob.build()
     return True
+
+
+def pytest_collection_modifyitems(config, items):
+    # GPU tests import torch lazily; nothing to change here beyond the marker
+    return None

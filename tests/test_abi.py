@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every symbol include/n2v.h declares
+(CPU only: host-side queries, no device work)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1805_00280_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    hdr = open(os.path.join(ROOT, "include", "n2v.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(n2v_\w+)\s*\(", hdr)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("libn2v.so not built (run __graft_entry__.build())")
+    return P.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(P.EXPORTS) == names
+
+
+def test_abi_version(lib):
+    assert lib.n2v_abi_version() == 1
+
+
+def test_defaults(lib):
+    g = P.GraphOpts()
+    lib.n2v_graph_opts_default(C.byref(g))
+    assert (g.d_rule, g.a_cap, g.validate) == (1024, 1024, 1)
+    o = P.exec_opts()
+    assert o.mode == P.MODE_AUTO and o.t_wave <= 1024
+    s = P.ServerOpts()
+    lib.n2v_server_opts_default(C.byref(s))
+    assert s.chunk_walks > 0 and s.max_queue > 0
+
+
+def test_rmat_workspace_query(lib):
+    ws, mm = C.c_size_t(), C.c_uint64()
+    prm = P.RmatParams(12, 16, 0.57, 0.19, 0.19, 12, 0)
+    assert lib.n2v_rmat_workspace(C.byref(prm), C.byref(ws), C.byref(mm)) == 0
+    assert mm.value == 2 * 16 * 4096
+    assert ws.value >= 2 * 8 * mm.value
+    bad = P.RmatParams(0, 16, 0.57, 0.19, 0.19, 12, 0)
+    assert lib.n2v_rmat_workspace(C.byref(bad), C.byref(ws), C.byref(mm)) == -1
+    assert b"bad parameters" in lib.n2v_last_error()
+    bad = P.RmatParams(12, 16, 0.7, 0.2, 0.2, 12, 0)
+    assert lib.n2v_rmat_workspace(C.byref(bad), C.byref(ws), C.byref(mm)) == -1
+
+
+def test_graph_workspace_query(lib):
+    ws = C.c_size_t()
+    assert lib.n2v_graph_workspace(1000, 5000, 0, C.byref(ws)) == 0
+    unweighted = ws.value
+    assert unweighted >= 16 * 1000 + 8 * 5000
+    assert lib.n2v_graph_workspace(1000, 5000, 1, C.byref(ws)) == 0
+    assert ws.value > unweighted
+    assert lib.n2v_graph_workspace(0, 5000, 0, C.byref(ws)) == -1
+
+
+def test_null_arguments_rejected_without_device_work(lib):
+    assert lib.n2v_walk_ex(None, None, 0, 0, 1, 1.0, 1.0, 0, None, 1, None, None, None, None, 0, None) == -1
+    assert lib.n2v_graph_destroy(None) == 0
+    assert lib.n2v_server_destroy(None) == 0
+    assert lib.n2v_poll(None, 1, None) == -1

@@ -1,0 +1,193 @@
+"""GPU walks against the oracle: bit-exact on the same seeds."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1805_00280_amd as P
+from paper_1805_00280_amd import workloads as WL
+from gpuhelp import (first_mismatch, gpu_graph_from_oracle, gpu_walk, oracle_rmat, oracle_walk, say,
+                     starts_tensor, torch_cuda, u32)
+
+pytestmark = pytest.mark.gpu
+
+SKEW = (0.65, 0.15, 0.15)
+DEF = (0.57, 0.19, 0.19)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    torch_cuda()
+    w = WL.C1
+    og = oracle_rmat(*w.rmat_args(), w.weighted)
+    return w, og, gpu_graph_from_oracle(og)
+
+
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+def test_scale12_workload_full_parity(c1, mode):
+    w, og, g = c1
+    say(f"[walk] {w.name} mode={mode} walks={w.walks}")
+    starts = w.starts()
+    want = oracle_walk(og, starts, w.L, w.p, w.q, w.seed)
+    got = gpu_walk(g, starts, w.L, w.p, w.q, w.seed, mode=mode)
+    assert first_mismatch(got, want) is None, first_mismatch(got, want)
+
+
+@pytest.mark.parametrize("opts", [
+    dict(t_wave=0), dict(t_wave=16), dict(t_wave=1024), dict(sparse_ratio=1), dict(sparse_ratio=100000),
+    dict(t_sparse=0), dict(waves_per_cu=4), dict(t_wave=0, sparse_ratio=1, waves_per_cu=1),
+])
+def test_execution_options_do_not_change_results(opts):
+    torch_cuda()
+    og = oracle_rmat(11, 16, *SKEW, 111, False)
+    g = gpu_graph_from_oracle(og, d_rule=48)
+    starts = np.tile(np.arange(og.n, dtype=np.uint32), 2)
+    say(f"[walk] exec opts {opts}")
+    want = oracle_walk(og, starts, 40, 0.25, 4.0, 77, d_rule=48)
+    got = gpu_walk(g, starts, 40, 0.25, 4.0, 77, **opts)
+    assert first_mismatch(got, want) is None, first_mismatch(got, want)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("d_rule,a_cap", [(0, 1024), (16, 1024), (0xFFFFFFFF, 1024), (1024, 1), (64, 2),
+                                          (0xFFFFFFFF, 1)])
+def test_rule_parameters(weighted, d_rule, a_cap):
+    torch_cuda()
+    og = oracle_rmat(10, 16, *SKEW, 10, weighted)
+    g = gpu_graph_from_oracle(og, d_rule=d_rule, a_cap=a_cap)
+    starts = np.arange(og.n, dtype=np.uint32)
+    p, q = (1.0, 0.5) if weighted else (0.5, 2.0)
+    say(f"[walk] rule d_rule={d_rule} a_cap={a_cap} weighted={weighted}")
+    for mode in (P.MODE_PERSISTENT, P.MODE_PLAIN):
+        want = oracle_walk(og, starts, 30, p, q, 5, d_rule=d_rule, a_cap=a_cap)
+        got = gpu_walk(g, starts, 30, p, q, 5, mode=mode)
+        assert first_mismatch(got, want) is None, (mode, first_mismatch(got, want))
+
+
+@pytest.mark.parametrize("p,q", list(itertools.product([0.25, 0.5, 1.0, 2.0, 4.0], repeat=2)))
+def test_all_p_q(p, q):
+    torch_cuda()
+    og = oracle_rmat(10, 16, *SKEW, 3, False)
+    g = gpu_graph_from_oracle(og, d_rule=32)
+    starts = np.arange(og.n, dtype=np.uint32)
+    want = oracle_walk(og, starts, 20, p, q, 9, d_rule=32)
+    got = gpu_walk(g, starts, 20, p, q, 9)
+    assert first_mismatch(got, want) is None, first_mismatch(got, want)
+
+
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+@pytest.mark.parametrize("pq", [(1.0, 0.5), (0.25, 4.0), (4.0, 0.25)])
+def test_weighted_with_hubs(mode, pq):
+    torch_cuda()
+    og = oracle_rmat(13, 16, *SKEW, 13, True)
+    g = gpu_graph_from_oracle(og, d_rule=100)
+    starts = np.arange(og.n, dtype=np.uint32)
+    say(f"[walk] weighted hubs mode={mode} pq={pq}")
+    want = oracle_walk(og, starts, 25, *pq, 31, d_rule=100)
+    got = gpu_walk(g, starts, 25, *pq, 31, mode=mode)
+    assert first_mismatch(got, want) is None, first_mismatch(got, want)
+
+
+def test_big_hubs_dense_and_sparse_paths():
+    # a graph whose hubs exceed the chunk-sum capacity of one wavefront
+    torch_cuda()
+    og = oracle_rmat(17, 16, *SKEW, 17, False)
+    deg = og.degree()
+    assert deg.max() > 512 * 128
+    g = gpu_graph_from_oracle(og, d_rule=64)
+    hubs = np.argsort(deg)[-64:].astype(np.uint32)
+    starts = np.repeat(hubs, 8)
+    for ratio in (1, 100000):
+        say(f"[walk] big hubs ratio={ratio}")
+        want = oracle_walk(og, starts, 12, 0.5, 2.0, 3, d_rule=64)
+        got = gpu_walk(g, starts, 12, 0.5, 2.0, 3, sparse_ratio=ratio)
+        assert first_mismatch(got, want) is None, first_mismatch(got, want)
+
+
+def test_walk_base_selects_stream(c1):
+    w, og, g = c1
+    starts = w.starts(0, 3000)
+    want = oracle_walk(og, starts, 15, w.p, w.q, w.seed, walk_base=123456)
+    got = gpu_walk(g, starts, 15, w.p, w.q, w.seed, walk_base=123456)
+    assert first_mismatch(got, want) is None
+
+
+def test_edge_cases(c1):
+    torch = torch_cuda()
+    w, og, g = c1
+    # no walks
+    out = g.walk(starts_tensor(torch, np.zeros(0, np.uint32)), 5, 1.0, 1.0, 1)
+    assert out.shape == (0, 6)
+    # one move
+    starts = w.starts(0, 500)
+    assert first_mismatch(gpu_walk(g, starts, 1, w.p, w.q, 2), oracle_walk(og, starts, 1, w.p, w.q, 2)) is None
+    # isolated starts
+    iso = np.nonzero(og.degree() == 0)[0][:100].astype(np.uint32)
+    got = gpu_walk(g, iso, 10, w.p, w.q, 2)
+    assert np.all(got[:, 0] == iso) and np.all(got[:, 1:] == O.SENT)
+    # start ids out of range: sentinel rows and a reported error
+    bad = np.array([0, og.n + 5, 1], dtype=np.uint32)
+    got = gpu_walk(g, bad, 4, w.p, w.q, 2)
+    assert np.all(got[1, 1:] == O.SENT)
+    assert first_mismatch(got[[0, 2]], oracle_walk(og, bad[[0, 2]], 4, w.p, w.q, 2, wids=[0, 2])) is None
+    with pytest.raises(P.N2VError):
+        g.check_starts()
+    g.check_starts()  # the flag was cleared
+    # bad p
+    with pytest.raises(P.N2VError):
+        g.walk(starts_tensor(torch, starts), 5, 0.3, 1.0, 1)
+
+
+def test_directed_dead_end_and_tiny_graphs():
+    torch_cuda()
+    g = O.CSR(np.array([0, 1, 2, 2], dtype=np.uint64), np.array([1, 2], dtype=np.uint32))
+    gg = gpu_graph_from_oracle(g)
+    got = gpu_walk(gg, np.array([0, 1, 2], dtype=np.uint32), 5, 1.0, 1.0, 1)
+    assert first_mismatch(got, oracle_walk(g, np.array([0, 1, 2], dtype=np.uint32), 5, 1.0, 1.0, 1)) is None
+    for edges, n in [([(0, 1)], 2), ([(0, i) for i in range(1, 40)], 40),
+                     ([(a, b) for a in range(12) for b in range(a + 1, 12)], 12)]:
+        og = O.CSR.from_edges(n, edges)
+        for d_rule in (0, 1024):
+            gg = gpu_graph_from_oracle(og, d_rule=d_rule)
+            starts = np.tile(np.arange(n, dtype=np.uint32), 30)
+            want = oracle_walk(og, starts, 15, 0.25, 4.0, 6, d_rule=d_rule)
+            got = gpu_walk(gg, starts, 15, 0.25, 4.0, 6)
+            assert first_mismatch(got, want) is None, (n, d_rule, first_mismatch(got, want))
+
+
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+def test_counts_and_checksum(mode):
+    torch = torch_cuda()
+    og = oracle_rmat(12, 16, *DEF, 5, False)
+    g = gpu_graph_from_oracle(og, d_rule=64)
+    starts = np.tile(np.arange(og.n, dtype=np.uint32), 3)
+    ref = O.walk(og, starts, 20, 2.0, 0.5, 5, d_rule=64, want_counts=True, nthreads=16)
+    cnt = torch.zeros(og.n, dtype=torch.int32, device="cuda")
+    cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    # three chunks with walk_base, counts accumulate
+    for lo in range(0, len(starts), 5000):
+        hi = min(lo + 5000, len(starts))
+        g.walk_counts(starts_tensor(torch, starts[lo:hi]), 20, 2.0, 0.5, 5, cnt, cs, walk_base=lo, mode=mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(cnt), ref["cnt"])
+    assert int(cs.cpu().numpy().view(np.uint64)[0]) == ref["checksum"]
+    # counts and walks together
+    out = torch.empty((len(starts), 21), dtype=torch.int32, device="cuda")
+    cnt.zero_()
+    cs.zero_()
+    g.walk_counts(starts_tensor(torch, starts), 20, 2.0, 0.5, 5, cnt, cs, out=out, mode=mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(out), ref["out"])
+    assert np.array_equal(u32(cnt), ref["cnt"])
+
+
+def test_autotune_keeps_results(c1):
+    w, og, g = c1
+    best, ms = g.autotune(4096, 40, w.p, w.q)
+    say(f"[tune] best={best.as_dict()} ms={ms:.3f}")
+    assert ms > 0
+    starts = w.starts(0, 8000)
+    want = oracle_walk(og, starts, w.L, w.p, w.q, w.seed)
+    got = gpu_walk(g, starts, w.L, w.p, w.q, w.seed)
+    assert first_mismatch(got, want) is None
