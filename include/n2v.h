@@ -152,7 +152,8 @@ typedef struct {
     uint32_t t_sparse;   /* hub moves use the sparse intersection when deg(t) <= t_sparse ... */
     uint32_t sparse_ratio; /* ... and deg(t) * sparse_ratio * log2(deg v) < deg(v) + deg(t) */
     uint32_t waves_per_cu; /* persistent grid size (0: occupancy-derived) */
-    uint32_t block;      /* persistent workgroup size: 64, 128 or 256 (0: 256) */
+    uint32_t block;      /* workgroup size (256) */
+    uint32_t memo;       /* 1: use the graph's pair sketches when attached (default 1) */
 } n2v_exec_opts;
 
 /* Fills execution defaults (tuned values when an autotune result was stored
@@ -180,6 +181,19 @@ int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, u
                 uint32_t L, float p, float q, uint64_t seed, const n2v_exec_opts *opts,
                 int outputs, uint32_t *out, uint32_t *cnt, uint64_t *checksum, void *ws,
                 size_t ws_bytes, void *stream);
+
+/* Pair sketches (unweighted graphs): memory in which walk calls memoise,
+ * for every traversed move (t -> v) at a vertex v of degree > d_rule, the
+ * exact number of members of N(t) in each of 64 equal segments of N(v) (as
+ * count + 1; 0 = unknown).  A later move along the same pair then recomputes
+ * one segment instead of the whole intersection.  Results never depend on the
+ * sketches: unknown entries are recomputed, and every known entry is exact.
+ * Each walk call clears them first, so no call reuses another call's work;
+ * concurrent calls on one graph share them.  n2v_graph_memo_bytes returns the
+ * size (hub entries x 128 bytes; 0 for weighted graphs); n2v_graph_set_memo
+ * attaches caller device memory (NULL detaches). */
+int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes);
+int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes);
 
 /* Synchronises the stream and returns N2V_EINVAL if any walk since the last
  * check had a start id >= n, N2V_EDEVICE if a kernel detected an internal

@@ -27,7 +27,7 @@ EXPORTS = [
     "n2v_last_error", "n2v_abi_version",
     "n2v_rmat_workspace", "n2v_rmat_generate",
     "n2v_graph_opts_default", "n2v_graph_workspace", "n2v_graph_create", "n2v_graph_destroy",
-    "n2v_graph_info", "n2v_graph_check",
+    "n2v_graph_info", "n2v_graph_check", "n2v_graph_memo_bytes", "n2v_graph_set_memo",
     "n2v_exec_opts_default", "n2v_walk", "n2v_walk_workspace", "n2v_walk_ex",
     "n2v_autotune_workspace", "n2v_autotune",
     "n2v_server_opts_default", "n2v_server_create", "n2v_server_destroy", "n2v_submit", "n2v_poll",
@@ -52,7 +52,8 @@ class GraphOpts(C.Structure):
 
 class ExecOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("t_wave", C.c_uint32), ("t_sparse", C.c_uint32),
-                ("sparse_ratio", C.c_uint32), ("waves_per_cu", C.c_uint32), ("block", C.c_uint32)]
+                ("sparse_ratio", C.c_uint32), ("waves_per_cu", C.c_uint32), ("block", C.c_uint32),
+                ("memo", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,6 +98,8 @@ def lib():
         "n2v_graph_destroy": ([vp], i32),
         "n2v_graph_info": ([vp, P(u32), P(u64), P(u32), P(u32), P(i32)], i32),
         "n2v_graph_check": ([vp, vp], i32),
+        "n2v_graph_memo_bytes": ([vp, P(sz)], i32),
+        "n2v_graph_set_memo": ([vp, vp, sz], i32),
         "n2v_exec_opts_default": ([vp, P(ExecOpts)], None),
         "n2v_walk": ([vp, vp, u32, u32, f32, f32, u64, vp, vp], i32),
         "n2v_walk_workspace": ([vp, u32, u32, P(ExecOpts), P(sz)], i32),
@@ -232,6 +235,20 @@ class Graph:
         n, m, d, a, w = C.c_uint32(), C.c_uint64(), C.c_uint32(), C.c_uint32(), C.c_int()
         check(lib().n2v_graph_info(self._h, C.byref(n), C.byref(m), C.byref(d), C.byref(a), C.byref(w)))
         return {"n": n.value, "m": m.value, "d_rule": d.value, "a_cap": a.value, "weighted": bool(w.value)}
+
+    def attach_memo(self):
+        """Allocates and attaches the pair-sketch memory (unweighted graphs); returns its bytes."""
+        b = C.c_size_t()
+        check(lib().n2v_graph_memo_bytes(self._h, C.byref(b)), "n2v_graph_memo_bytes")
+        if b.value == 0:
+            return 0
+        self.memo = _alloc(b.value, self.device)
+        check(lib().n2v_graph_set_memo(self._h, _ptr(self.memo), self.memo.numel()), "n2v_graph_set_memo")
+        return b.value
+
+    def detach_memo(self):
+        check(lib().n2v_graph_set_memo(self._h, None, 0), "n2v_graph_set_memo")
+        self.memo = None
 
     def check_starts(self, stream=None):
         check(lib().n2v_graph_check(self._h, _stream(stream)), "n2v_graph_check")

@@ -14,6 +14,10 @@ namespace n2v {
 
 constexpr uint32_t SENT = 0xFFFFFFFFu;
 constexpr int WAVE = 64;
+// Segments per pair sketch: a sketch of the move (t -> v) at a hub v holds,
+// for each of up to MEMO_SEGS segments of N(v), one plus the number of
+// members of N(t) in that segment (0 = not known yet).
+constexpr int MEMO_SEGS = 64;
 
 // ---------------------------------------------------------------- errors
 int set_error(int code, const char *fmt, ...);
@@ -40,6 +44,8 @@ struct DevGraph {
     const uint32_t *adj;   // m, rows strictly ascending
     const uint16_t *wt;    // m, or null for an unweighted graph
     const uint64_t *wsum;  // n: row weight sums (weighted graphs only)
+    const uint64_t *hbase; // n+1: first memo entry of each row of degree > d_rule
+    uint16_t *memo;        // pair sketches (hbase[n] entries of MEMO_SEGS u16) or null
     uint32_t *status;      // device flags: bit 0 = a start id was out of range
     uint32_t n;
     uint64_t m;
@@ -129,18 +135,34 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v)
     return v;
 }
 
+// Wave-uniform values live in scalar registers.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uni64(uint64_t v)
+{
+    return join64(__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)), __builtin_amdgcn_readfirstlane((uint32_t)v));
+}
+
+// Value of lane `src` (uniform) in a scalar register.
+__device__ __forceinline__ uint32_t lane_val(uint32_t v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
+__device__ __forceinline__ uint64_t lane_val64(uint64_t v, int src)
+{
+    return join64(__builtin_amdgcn_readlane((uint32_t)(v >> 32), src), __builtin_amdgcn_readlane((uint32_t)v, src));
+}
+
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v)
 {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += shfl_xor64(v, m);
-    return v;
+    return uni64(v);
 }
 
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
 {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
-    return v;
+    return uni(v);
 }
 
 __device__ __forceinline__ int first_lane(uint64_t mask) { return __ffsll((unsigned long long)mask) - 1; }
@@ -174,4 +196,6 @@ struct n2v_graph {
     int device;
     bool has_tuned;
     n2v_exec_opts tuned;
+    uint64_t hub_entries;   // entries in rows of degree > d_rule
+    size_t memo_bytes;      // attached sketch memory (0: none)
 };

@@ -78,6 +78,16 @@ __global__ __launch_bounds__(256) void k_derive(const uint64_t *__restrict__ off
     if (flags) atomicOr(bad, flags);
 }
 
+// hbase[v] = deg(v) when deg(v) > d_rule, else 0 (scanned afterwards).
+__global__ void k_hub_len(const uint64_t *__restrict__ off, uint32_t n, uint32_t d_rule, uint64_t *__restrict__ hb)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride) {
+        const uint64_t d = v < n ? off[v + 1] - off[v] : 0;
+        hb[v] = d > d_rule ? d : 0;
+    }
+}
+
 __global__ void k_zero_u32(uint32_t *p, uint32_t n)
 {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
@@ -87,6 +97,8 @@ struct GraphLayout {
     VRec *vrec;
     uint2 *erec;
     uint64_t *wsum;
+    uint64_t *hbase;
+    void *scan;
     uint32_t *status;
 };
 
@@ -97,6 +109,8 @@ size_t graph_layout(uint32_t n, uint64_t m, int weighted, void *ws, size_t ws_by
     L->vrec = c.take<VRec>((uint64_t)n + 1);
     L->erec = c.take<uint2>(m ? m : 1);
     L->wsum = weighted ? c.take<uint64_t>((uint64_t)n + 1) : nullptr;
+    L->hbase = c.take<uint64_t>((uint64_t)n + 1);
+    L->scan = c.take<char>(scan_scratch_bytes((uint64_t)n + 1));
     return c.total();
 }
 
@@ -172,8 +186,19 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
         N2V_HIP(hipStreamSynchronize(st));
         if (bad) return set_error(N2V_EGRAPH, "n2v_graph_create: CSR is not symmetric (flags 0x%x)", bad);
     }
+    hipLaunchKernelGGL(k_hub_len, dim3(grid_for_waves(n)), dim3(256), 0, st, off, n, o.d_rule, L.hbase);
+    N2V_HIP(hipGetLastError());
+    int rc = exclusive_scan_u64(L.hbase, (uint64_t)n + 1, L.scan, st);
+    if (rc) return rc;
+    uint64_t hub_entries = 0;
+    N2V_HIP(hipMemcpyAsync(&hub_entries, L.hbase + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    N2V_HIP(hipStreamSynchronize(st));
     n2v_graph *g = (n2v_graph *)calloc(1, sizeof(n2v_graph));
     if (!g) return set_error(N2V_ENOMEM, "n2v_graph_create: host allocation failed");
+    g->dg.hbase = L.hbase;
+    g->dg.memo = nullptr;
+    g->hub_entries = hub_entries;
+    g->memo_bytes = 0;
     g->dg.vrec = L.vrec;
     g->dg.erec = L.erec;
     g->dg.adj = adj;
@@ -208,6 +233,31 @@ extern "C" int n2v_graph_info(const n2v_graph *g, uint32_t *n, uint64_t *m, uint
     if (d_rule) *d_rule = g->dg.d_rule;
     if (a_cap) *a_cap = g->dg.a_cap;
     if (weighted) *weighted = g->weighted;
+    return N2V_OK;
+}
+
+extern "C" int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes)
+{
+    if (!g || !bytes) return set_error(N2V_EINVAL, "n2v_graph_memo_bytes: null argument");
+    *bytes = g->weighted ? 0 : (size_t)g->hub_entries * MEMO_SEGS * sizeof(uint16_t);
+    return N2V_OK;
+}
+
+extern "C" int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes)
+{
+    if (!g) return set_error(N2V_EINVAL, "n2v_graph_set_memo: null graph");
+    if (!mem) {
+        g->dg.memo = nullptr;
+        g->memo_bytes = 0;
+        return N2V_OK;
+    }
+    size_t need = 0;
+    n2v_graph_memo_bytes(g, &need);
+    if (need == 0) return set_error(N2V_EINVAL, "n2v_graph_set_memo: weighted graphs keep no pair sketches");
+    if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
+    if (((uintptr_t)mem & 255) != 0) return set_error(N2V_EINVAL, "n2v_graph_set_memo: memory not 256-byte aligned");
+    g->dg.memo = (uint16_t *)mem;
+    g->memo_bytes = bytes;
     return N2V_OK;
 }
 

@@ -51,8 +51,9 @@ namespace {
 
 constexpr int HCH = 512;            // hub sub-chunk: 8 entries per lane
 constexpr int HEPL = HCH / WAVE;
-constexpr int NSUPER = 128;         // chunk sums held per wavefront
+constexpr int NSUPER = MEMO_SEGS;   // segments (chunk sums) per hub row
 constexpr int SPCAP = 512;          // specials held by the sparse path
+constexpr int YB = 4;               // N(t) entries per lane per streaming step
 
 // LDS of one wavefront for hub moves (6 KiB).
 struct HubLds {
@@ -67,13 +68,31 @@ struct HubLds {
         } sp;
     } a;
     union {
-        struct {
-            uint64_t csum[NSUPER];
-            uint32_t cy[NSUPER];
-        } d;
+        uint64_t csum[NSUPER];
         int32_t dl[HCH];
     } b;
 };
+
+// The state of lane o in scalar registers.
+__device__ __forceinline__ WS bcast(const WS &s, int o)
+{
+    WS w;
+    w.job = lane_val(s.job, o);
+    w.i = lane_val(s.i, o);
+    w.s = lane_val(s.s, o);
+    w.v = lane_val(s.v, o);
+    w.t = lane_val(s.t, o);
+    w.vo = lane_val64(s.vo, o);
+    w.vd = lane_val(s.vd, o);
+    w.vw = lane_val(s.vw, o);
+    w.to = lane_val64(s.to, o);
+    w.td = lane_val(s.td, o);
+    w.pos_t = lane_val(s.pos_t, o);
+    w.jprev = lane_val(s.jprev, o);
+    return w;
+}
+
+__device__ __forceinline__ WS uniform_ws(const WS &s) { return bcast(s, 0); }
 
 __device__ __forceinline__ uint32_t amax3(const JobCtx &J)
 {
@@ -159,8 +178,9 @@ __device__ bool thread_reject(const Exec &E, const JobCtx &J, const WS &st, uint
 }
 
 // Wave class: lanes take attempts k0 + lane; the lowest accepting one wins.
-__device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st, uint32_t &j_out)
+__device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, uint32_t &j_out)
 {
+    const WS st = uniform_ws(st_in);
     const int l = lane_id();
     for (uint32_t k0 = 0; k0 < E.g.a_cap; k0 += WAVE) {
         const uint32_t k = k0 + l;
@@ -168,7 +188,7 @@ __device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st, uint32
         const bool acc = k < E.g.a_cap && attempt(E, J, st, k, j);
         const uint64_t m = ballot(acc);
         if (m) {
-            j_out = shfl32(j, first_lane(m));
+            j_out = lane_val(j, first_lane(m));
             return true;
         }
     }
@@ -177,35 +197,39 @@ __device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st, uint32
 
 // ------------------------------------------------------------------ hubs
 // Stages N(v)[j0, j0+cnt) in LDS and flags the members of N(t), streaming
-// N(t) from ypos (advanced past every value <= the chunk's last entry).
-__device__ void dense_flags(const Exec &E, const WS &st, HubLds &L, uint64_t j0, uint32_t cnt, uint64_t &ypos)
+// N(t) from ypos (advanced past every value <= the chunk's last entry).  The
+// chunk and the first block of N(t) are loaded together.  Returns the number
+// of flagged entries.
+__device__ uint32_t dense_flags(const Exec &E, const WS &st, HubLds &L, uint64_t j0, uint32_t cnt, uint64_t &ypos)
 {
     const int l = lane_id();
     const uint32_t *__restrict__ adj = E.g.adj;
+    const uint64_t td = st.td;
+    uint32_t xv[HEPL], y[YB];
 #pragma unroll
     for (int e = 0; e < HEPL; ++e) {
         const uint32_t i = e * WAVE + l;
-        L.a.d.xs[i] = i < cnt ? adj[st.vo + j0 + i] : 0xFFFFFFFFu;
-        L.a.d.flag[i] = 0;
+        xv[e] = i < cnt ? adj[st.vo + j0 + i] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int b = 0; b < YB; ++b) {
+        const uint64_t idx = ypos + b * WAVE + l;
+        y[b] = idx < td ? adj[st.to + idx] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int e = 0; e < HEPL; ++e) {
+        L.a.d.xs[e * WAVE + l] = xv[e];
+        L.a.d.flag[e * WAVE + l] = 0;
     }
     wave_lds_sync();
     const uint32_t xlast = L.a.d.xs[cnt - 1];
-    const uint64_t td = st.td;
-    while (ypos < td) {
-        uint32_t y[4];
-        bool in[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint64_t idx = ypos + b * WAVE + l;
-            const bool valid = idx < td;
-            y[b] = valid ? adj[st.to + idx] : 0xFFFFFFFFu;
-            in[b] = valid && y[b] <= xlast;
-        }
+    for (;;) {
         uint32_t nin = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            nin += __popcll(ballot(in[b]));
-            if (in[b]) {
+        for (int b = 0; b < YB; ++b) {
+            const bool in = ypos + b * WAVE + l < td && y[b] <= xlast;
+            nin += __popcll(ballot(in));
+            if (in) {
                 uint32_t lo = 0, hi = cnt;
                 while (lo < hi) {
                     const uint32_t mid = (lo + hi) >> 1;
@@ -216,9 +240,18 @@ __device__ void dense_flags(const Exec &E, const WS &st, HubLds &L, uint64_t j0,
             }
         }
         ypos += nin;
-        if (nin < 4 * WAVE) break;
+        if (nin < YB * WAVE || ypos >= td) break;
+#pragma unroll
+        for (int b = 0; b < YB; ++b) {
+            const uint64_t idx = ypos + b * WAVE + l;
+            y[b] = idx < td ? adj[st.to + idx] : 0xFFFFFFFFu;
+        }
     }
     wave_lds_sync();
+    uint32_t c = 0;
+#pragma unroll
+    for (int e = 0; e < HEPL; ++e) c += L.a.d.flag[e * WAVE + l];
+    return wave_sum32(c);
 }
 
 __device__ __forceinline__ uint64_t dense_pi(const Exec &E, const JobCtx &J, const WS &st, const HubLds &L,
@@ -255,57 +288,91 @@ __device__ uint32_t dense_chunk_locate(const Exec &E, const JobCtx &J, const WS 
         const uint64_t inc = wave_incl_scan(pi);
         const uint64_t m = ballot(i < cnt && base + inc > r);
         if (m) return (uint32_t)(j0 + e * WAVE + first_lane(m));
-        base += shfl64(inc, WAVE - 1);
+        base += lane_val64(inc, WAVE - 1);
     }
     return SENT;
 }
 
-// Dense inverse CDF of a second-order move over all of N(v).
+// Sum of pi over N(v)[j0, j0+len) of an unweighted row with c members of N(t).
+__device__ __forceinline__ uint64_t seg_pi(const JobCtx &J, const WS &st, uint64_t j0, uint64_t len, uint32_t c)
+{
+    uint64_t s = (uint64_t)J.A_out * len + (uint64_t)((int64_t)((int32_t)A_COM - (int32_t)J.A_out) * (int64_t)c);
+    if (st.pos_t >= j0 && st.pos_t < j0 + len) s += (uint64_t)((int64_t)J.A_ret - (int64_t)J.A_out);
+    return s;
+}
+
+// Dense inverse CDF of a second-order move over all of N(v): per-segment sums
+// (from the pair sketch when it is known, else by a merge-intersection pass
+// that also fills the sketch), then one segment is recomputed to find the
+// entry whose prefix sum first exceeds r.
 __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, uint64_t R1)
 {
     const int l = lane_id();
     const uint64_t dv = st.vd;
     const uint64_t nsub = (dv + HCH - 1) / HCH;
-    const uint64_t G = (nsub + NSUPER - 1) / NSUPER;
+    const uint64_t G = (nsub + NSUPER - 1) / NSUPER;   // sub-chunks per segment
     const uint64_t nsup = (nsub + G - 1) / G;
-    uint64_t ypos = 0;
-    if (st.td) ypos = lower_bound_g(E.g.adj, st.to, st.to + st.td, E.g.adj[st.vo]) - st.to;
-    uint64_t S = 0;
-    for (uint64_t sp = 0; sp < nsup; ++sp) {
-        const uint64_t y0 = ypos;
-        uint64_t sum = 0;
-        const uint64_t sub_end = std::min(nsub, (sp + 1) * G);
-        for (uint64_t sub = sp * G; sub < sub_end; ++sub) {
-            const uint64_t j0 = sub * HCH;
-            const uint32_t cnt = (uint32_t)std::min<uint64_t>(HCH, dv - j0);
-            dense_flags(E, st, L, j0, cnt, ypos);
-            sum += dense_chunk_sum(E, J, st, L, j0, cnt);
-            wave_lds_sync();
+    const uint64_t seglen = G * HCH;
+    const bool weighted = E.g.wt != nullptr;
+    uint16_t *row = nullptr;
+    if (E.g.memo && !weighted && st.pos_t != SENT)
+        row = E.g.memo + (E.g.hbase[st.v] + st.pos_t) * (uint64_t)MEMO_SEGS;
+    bool warm = false;
+    uint32_t known = 1;
+    if (row) {
+        if ((uint64_t)l < nsup) known = row[l];
+        warm = ballot(known == 0) == 0;
+    }
+    uint64_t S;
+    if (warm) {
+        uint64_t pi = 0;
+        if ((uint64_t)l < nsup) {
+            const uint64_t a = l * seglen;
+            const uint64_t len = std::min(seglen, dv - a);
+            pi = seg_pi(J, st, a, len, known - 1);
+            L.b.csum[l] = pi;
         }
-        if (l == 0) {
-            L.b.d.csum[sp] = sum;
-            L.b.d.cy[sp] = (uint32_t)y0;
+        S = wave_sum(pi);
+    } else {
+        uint64_t ypos = st.td ? lower_bound_g(E.g.adj, st.to, st.to + st.td, E.g.adj[st.vo]) - st.to : 0;
+        uint32_t mine = 0;
+        S = 0;
+        for (uint64_t sp = 0; sp < nsup; ++sp) {
+            uint64_t sum = 0;
+            uint32_t csp = 0;
+            const uint64_t sub_end = std::min(nsub, (sp + 1) * G);
+            for (uint64_t sub = sp * G; sub < sub_end; ++sub) {
+                const uint64_t j0 = sub * HCH;
+                const uint32_t cnt = (uint32_t)std::min<uint64_t>(HCH, dv - j0);
+                const uint32_t c = dense_flags(E, st, L, j0, cnt, ypos);
+                sum += weighted ? dense_chunk_sum(E, J, st, L, j0, cnt) : seg_pi(J, st, j0, cnt, c);
+                csp += c;
+                wave_lds_sync();
+            }
+            if (l == 0) L.b.csum[sp] = sum;
+            if ((uint64_t)l == sp) mine = csp;
+            S += sum;
         }
-        S += sum;
+        if (row && (uint64_t)l < nsup) __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
     }
     wave_lds_sync();
     const uint64_t r = hi64(R1, S);
     uint64_t base = 0, spx = nsup - 1;
-    for (uint64_t b0 = 0; b0 < nsup; b0 += WAVE) {
-        const uint64_t idx = b0 + l;
-        const uint64_t c = idx < nsup ? L.b.d.csum[idx] : 0;
+    {
+        const uint64_t c = (uint64_t)l < nsup ? L.b.csum[l] : 0;
         const uint64_t inc = wave_incl_scan(c);
-        const uint64_t m = ballot(idx < nsup && base + inc > r);
+        const uint64_t m = ballot((uint64_t)l < nsup && inc > r);
         if (m) {
             const int f = first_lane(m);
-            spx = b0 + f;
-            base += shfl64(inc - c, f);
-            break;
+            spx = f;
+            base = lane_val64(inc - c, f);
+        } else {
+            base = lane_val64(inc - c, (int)(nsup - 1));
         }
-        base += shfl64(inc, WAVE - 1);
     }
-    ypos = L.b.d.cy[spx];
     wave_lds_sync();
+    const uint64_t x0 = spx * seglen;
+    uint64_t ypos = st.td ? lower_bound_g(E.g.adj, st.to, st.to + st.td, E.g.adj[st.vo + x0]) - st.to : 0;
     const uint64_t sub_end = std::min(nsub, (spx + 1) * G);
     for (uint64_t sub = spx * G; sub < sub_end; ++sub) {
         const uint64_t j0 = sub * HCH;
@@ -351,7 +418,7 @@ __device__ uint32_t weighted_scan_locate(const Exec &E, const WS &st, HubLds &L,
                 wave_lds_sync();
                 return (uint32_t)(j0 + e * WAVE + first_lane(m));
             }
-            base += shfl64(inc, WAVE - 1);
+            base += lane_val64(inc, WAVE - 1);
         }
         wave_lds_sync();
     }
@@ -430,20 +497,18 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
         const int64_t Dincl = D + inc;
         const bool cross = valid && (int64_t)J.A_out * (q + 1) + Dincl > (int64_t)r;
         const uint64_t m = ballot(cross);
-        const int64_t qleft = (int64_t)shfl64((uint64_t)q, l > 0 ? l - 1 : 0);
         if (m) {
             const int f = first_lane(m);
-            const int64_t qf = (int64_t)shfl64((uint64_t)q, f);
-            const int64_t Dexcl = (int64_t)shfl64((uint64_t)(Dincl - dl), f);
-            const int64_t qlf = (int64_t)shfl64((uint64_t)qleft, f);
-            const int64_t qp = f > 0 ? qlf : qprev;
+            const int64_t qf = (int64_t)lane_val64((uint64_t)q, f);
+            const int64_t Dexcl = (int64_t)lane_val64((uint64_t)(Dincl - dl), f);
+            const int64_t qp = f > 0 ? (int64_t)lane_val64((uint64_t)q, f - 1) : qprev;
             int64_t ig = ((int64_t)r - Dexcl) / (int64_t)J.A_out;
             if (ig < qp + 1) ig = qp + 1;
             return (uint32_t)(ig < qf ? ig : qf);
         }
-        D += (int64_t)shfl64((uint64_t)inc, WAVE - 1);
+        D += (int64_t)lane_val64((uint64_t)inc, WAVE - 1);
         const uint32_t last = c - 1 - b < (uint32_t)(WAVE - 1) ? c - 1 - b : (uint32_t)(WAVE - 1);
-        qprev = (int64_t)shfl64((uint64_t)q, (int)last);
+        qprev = (int64_t)lane_val64((uint64_t)q, (int)last);
     }
     int64_t ig = ((int64_t)r - D) / (int64_t)J.A_out;
     if (ig < qprev + 1) ig = qprev + 1;
@@ -458,8 +523,9 @@ __device__ __forceinline__ bool use_sparse(const Exec &E, const WS &st)
 }
 
 // Inverse CDF of one move by a wavefront (state uniform across lanes).
-__device__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &st, uint32_t kidx, HubLds &L)
+__device__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &st_in, uint32_t kidx, HubLds &L)
 {
+    const WS st = uniform_ws(st_in);
     const R4 rr = philox(J.k0, J.k1, J.wbase + st.i, st.s, kidx, 0u);
     const uint64_t R1 = join64(rr.x, rr.y);
     if (st.s == 0) {
@@ -472,24 +538,6 @@ __device__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &s
         j = st.vd - 1;
     }
     return j;
-}
-
-__device__ WS bcast(const WS &s, int o)
-{
-    WS w;
-    w.job = shfl32(s.job, o);
-    w.i = shfl32(s.i, o);
-    w.s = shfl32(s.s, o);
-    w.v = shfl32(s.v, o);
-    w.t = shfl32(s.t, o);
-    w.vo = shfl64(s.vo, o);
-    w.vd = shfl32(s.vd, o);
-    w.vw = shfl32(s.vw, o);
-    w.to = shfl64(s.to, o);
-    w.td = shfl32(s.td, o);
-    w.pos_t = shfl32(s.pos_t, o);
-    w.jprev = shfl32(s.jprev, o);
-    return w;
 }
 
 template <bool WALKS>
@@ -638,7 +686,7 @@ __global__ __launch_bounds__(PBLOCK) void k_persistent(Exec E, Src S)
             WS w = bcast(st, o);
             w.job = __builtin_amdgcn_readfirstlane(w.job);
             const JobCtx J = S.ctx(w.job);
-            uint32_t k = shfl32(pk, o);
+            uint32_t k = lane_val(pk, o);
             bool alive = true;
             for (;;) {
                 uint32_t j;
@@ -769,17 +817,17 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
 
 // One workgroup-resident wavefront per hub move of this superstep.
 template <bool WALKS, bool COUNTS>
-__global__ __launch_bounds__(256) void k_plain_hub(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
+__global__ __launch_bounds__(256, 4) void k_plain_hub(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
                                                    const uint32_t *__restrict__ hubq, const uint32_t *__restrict__ hubn)
 {
     __shared__ HubLds lds[256 / WAVE];
     HubLds &L = lds[threadIdx.x / WAVE];
-    const uint32_t gw = blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    const uint32_t gw = uni(blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE);
     const uint32_t nw = gridDim.x * (256 / WAVE);
     const uint32_t n = *hubn;
     uint64_t csum = 0;
     for (uint32_t q = gw; q < n; q += nw) {
-        const uint32_t item = hubq[q];
+        const uint32_t item = uni(hubq[q]);
         const uint32_t i = item & 0x7FFFFFFFu;
         const uint32_t kidx = (item & 0x80000000u) ? E.g.a_cap : 0u;
         WS st;
@@ -791,6 +839,12 @@ __global__ __launch_bounds__(256) void k_plain_hub(Exec E, OneJob S, uint32_t s,
         csum = wave_sum(csum);
         if (lane_id() == 0 && csum) atomicAdd(S.c.checksum, (unsigned long long)csum);
     }
+}
+
+__global__ void k_zero64(uint32_t *p, uint64_t n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
 }
 
 __global__ void k_zero(uint32_t *p, uint32_t n)
@@ -893,6 +947,7 @@ int walk_multipliers(float p, float q, uint32_t *A_ret, uint32_t *A_out)
 void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E)
 {
     E->g = g->dg;
+    if (!o.memo) E->g.memo = nullptr;
     E->t_wave = o.t_wave;
     E->t_sparse = o.t_sparse;
     E->sparse_ratio = o.sparse_ratio < 1 ? 1 : o.sparse_ratio;
@@ -940,6 +995,7 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
     o->sparse_ratio = 2;
     o->waves_per_cu = 0;
     o->block = 256;
+    o->memo = 1;
 }
 
 extern "C" int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_t L, const n2v_exec_opts *opts,
@@ -965,11 +1021,11 @@ extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t 
     if (!(outputs & (N2V_OUT_WALKS | N2V_OUT_COUNTS)) || (outputs & ~(N2V_OUT_WALKS | N2V_OUT_COUNTS)))
         return set_error(N2V_EINVAL, "n2v_walk: outputs must be a nonempty mask of N2V_OUT_WALKS | N2V_OUT_COUNTS");
     const bool W = outputs & N2V_OUT_WALKS, C = outputs & N2V_OUT_COUNTS;
-    if (W && !out) return set_error(N2V_EINVAL, "n2v_walk: null out");
-    if (C && (!cnt || !checksum)) return set_error(N2V_EINVAL, "n2v_walk: null cnt or checksum");
     if (walk_base + (uint64_t)n_starts > (1ull << 32)) return set_error(N2V_EINVAL, "n2v_walk: walk ids exceed 2^32");
     if (n_starts >= 0x80000000u) return set_error(N2V_EINVAL, "n2v_walk: at most 2^31-1 walks per call");
     if (n_starts == 0) return N2V_OK;
+    if (W && !out) return set_error(N2V_EINVAL, "n2v_walk: null out");
+    if (C && (!cnt || !checksum)) return set_error(N2V_EINVAL, "n2v_walk: null cnt or checksum");
     if (!starts) return set_error(N2V_EINVAL, "n2v_walk: null starts");
     n2v_exec_opts o;
     n2v_exec_opts_default(g, &o);
@@ -990,6 +1046,12 @@ extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t 
     S.starts = starts;
     S.n = n_starts;
     hipStream_t st = (hipStream_t)stream;
+    if (E.g.memo) {  // sketches are rebuilt within each call
+        const uint64_t words = (uint64_t)g->memo_bytes / 4;
+        hipLaunchKernelGGL(k_zero64, dim3((uint32_t)std::min<uint64_t>((words + 255) / 256, 65536)), dim3(256), 0, st,
+                           (uint32_t *)E.g.memo, words);
+        N2V_HIP(hipGetLastError());
+    }
 
     if (o.mode == N2V_MODE_PLAIN) {
         const size_t need = plain_ws(n_starts, L);

@@ -89,18 +89,29 @@ def test_weighted_with_hubs(mode, pq):
     assert first_mismatch(got, want) is None, first_mismatch(got, want)
 
 
+def _two_hub_graph():
+    # hub 0 adjacent to every other vertex (degree beyond the 128 x 512 entries
+    # one wavefront keeps chunk sums for), hub 1 to every third vertex, and a
+    # sparse random layer so that low-degree vertices have common neighbours
+    n = 70_000
+    rng = np.random.default_rng(7)
+    edges = [(0, v) for v in range(1, n)] + [(1, v) for v in range(3, n, 3)]
+    a = rng.integers(2, n, size=60_000)
+    b = rng.integers(2, n, size=60_000)
+    edges += list(zip(a.tolist(), b.tolist()))
+    return O.CSR.from_edges(n, edges)
+
+
 def test_big_hubs_dense_and_sparse_paths():
-    # a graph whose hubs exceed the chunk-sum capacity of one wavefront
     torch_cuda()
-    og = oracle_rmat(17, 16, *SKEW, 17, False)
-    deg = og.degree()
-    assert deg.max() > 512 * 128
+    og = _two_hub_graph()
+    assert og.degree().max() > 512 * 128
     g = gpu_graph_from_oracle(og, d_rule=64)
-    hubs = np.argsort(deg)[-64:].astype(np.uint32)
-    starts = np.repeat(hubs, 8)
+    starts = np.concatenate([np.repeat(np.arange(6, dtype=np.uint32), 40),
+                             np.arange(2, 2000, dtype=np.uint32)])
+    want = oracle_walk(og, starts, 12, 0.5, 2.0, 3, d_rule=64)
     for ratio in (1, 100000):
         say(f"[walk] big hubs ratio={ratio}")
-        want = oracle_walk(og, starts, 12, 0.5, 2.0, 3, d_rule=64)
         got = gpu_walk(g, starts, 12, 0.5, 2.0, 3, sparse_ratio=ratio)
         assert first_mismatch(got, want) is None, first_mismatch(got, want)
 
@@ -191,3 +202,24 @@ def test_autotune_keeps_results(c1):
     want = oracle_walk(og, starts, w.L, w.p, w.q, w.seed)
     got = gpu_walk(g, starts, w.L, w.p, w.q, w.seed)
     assert first_mismatch(got, want) is None
+
+
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+def test_pair_sketches_keep_results(mode):
+    # many walks from the hubs traverse the same hub pairs again and again, so
+    # most dense hub moves read a sketch written earlier in the same call
+    torch_cuda()
+    og = oracle_rmat(14, 16, *SKEW, 14, False)
+    g = gpu_graph_from_oracle(og, d_rule=40)
+    assert g.attach_memo() > 0
+    deg = og.degree()
+    hubs = np.argsort(deg)[-256:].astype(np.uint32)
+    starts = np.concatenate([np.repeat(hubs, 64), np.arange(og.n, dtype=np.uint32)])
+    want = oracle_walk(og, starts, 30, 0.25, 4.0, 8, d_rule=40)
+    for rep in range(2):  # the second call starts from cleared sketches again
+        say(f"[walk] sketches mode={mode} rep={rep}")
+        got = gpu_walk(g, starts, 30, 0.25, 4.0, 8, mode=mode, sparse_ratio=100000)
+        assert first_mismatch(got, want) is None, first_mismatch(got, want)
+    got = gpu_walk(g, starts, 30, 0.25, 4.0, 8, mode=mode, memo=0)
+    assert first_mismatch(got, want) is None
+    g.detach_memo()
