@@ -14,7 +14,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libn2v.so")
+# N2V_LIBRARY selects another build of the same library (e.g. a variant under test)
+LIB_PATH = os.environ.get("N2V_LIBRARY") or os.path.join(_HERE, "libn2v.so")
 SENT = 0xFFFFFFFF
 
 N2V_OK, N2V_PENDING = 0, 1

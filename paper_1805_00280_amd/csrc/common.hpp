@@ -18,6 +18,10 @@ constexpr int WAVE = 64;
 // for each of up to MEMO_SEGS segments of N(v), one plus the number of
 // members of N(t) in that segment (0 = not known yet).
 constexpr int MEMO_SEGS = 64;
+// Walk counters a graph hands out round-robin to persistent launches: up to
+// this many launches on one graph may overlap.
+constexpr int CURSOR_SLOTS = 64;
+constexpr int CURSOR_STRIDE = 64;  // words between counters (one per 256 bytes)
 
 // ---------------------------------------------------------------- errors
 int set_error(int code, const char *fmt, ...);
@@ -47,6 +51,7 @@ struct DevGraph {
     const uint64_t *hbase; // n+1: first memo entry of each row of degree > d_rule
     uint16_t *memo;        // pair sketches (hbase[n] entries of MEMO_SEGS u16) or null
     uint32_t *status;      // device flags: bit 0 = a start id was out of range
+    uint32_t *cursors;     // CURSOR_SLOTS walk counters, one per concurrent call
     uint32_t n;
     uint64_t m;
     uint32_t d_rule;
@@ -197,5 +202,6 @@ struct n2v_graph {
     bool has_tuned;
     n2v_exec_opts tuned;
     uint64_t hub_entries;   // entries in rows of degree > d_rule
+    uint32_t next_cursor;   // round-robin counter slot
     size_t memo_bytes;      // attached sketch memory (0: none)
 };

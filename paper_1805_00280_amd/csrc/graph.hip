@@ -100,12 +100,14 @@ struct GraphLayout {
     uint64_t *hbase;
     void *scan;
     uint32_t *status;
+    uint32_t *cursors;
 };
 
 size_t graph_layout(uint32_t n, uint64_t m, int weighted, void *ws, size_t ws_bytes, GraphLayout *L)
 {
     Carver c(ws, ws_bytes);
     L->status = c.take<uint32_t>(64);
+    L->cursors = c.take<uint32_t>((uint64_t)CURSOR_SLOTS * CURSOR_STRIDE);
     L->vrec = c.take<VRec>((uint64_t)n + 1);
     L->erec = c.take<uint2>(m ? m : 1);
     L->wsum = weighted ? c.take<uint64_t>((uint64_t)n + 1) : nullptr;
@@ -205,6 +207,8 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
     g->dg.wt = wt;
     g->dg.wsum = L.wsum;
     g->dg.status = L.status;
+    g->dg.cursors = L.cursors;
+    g->next_cursor = 0;
     g->dg.n = n;
     g->dg.m = m;
     g->dg.d_rule = o.d_rule;

@@ -222,6 +222,7 @@ struct n2v_server {
         }
         h->njobs = nj;
         h->total = total;
+        h->cursor = 0;
         h->jstart[nj] = total;
         return total;
     }

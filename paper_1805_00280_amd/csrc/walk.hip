@@ -49,18 +49,21 @@ struct WS {
 
 namespace {
 
-constexpr int HCH = 512;            // hub sub-chunk: 8 entries per lane
+constexpr int HCH = 512;            // weighted scan chunk: 8 entries per lane
 constexpr int HEPL = HCH / WAVE;
-constexpr int NSUPER = MEMO_SEGS;   // segments (chunk sums) per hub row
+constexpr int TX = 512;             // dense merge: N(v) tile, 8 entries per lane
+constexpr int XPL = TX / WAVE;
+constexpr int YPL = 16;             // dense merge: N(t) block of 16 x 64 entries
+constexpr int YFIRST = 4;           // entries per lane of the first N(t) block of a tile
+constexpr int NSUPER = MEMO_SEGS;   // segments (sums) per hub row
 constexpr int SPCAP = 512;          // specials held by the sparse path
-constexpr int YB = 4;               // N(t) entries per lane per streaming step
 
 // LDS of one wavefront for hub moves (6 KiB).
 struct HubLds {
     union {
         struct {
-            uint32_t xs[HCH];
-            uint8_t flag[HCH];
+            uint32_t xs[TX];
+            uint8_t flag[TX];
         } d;
         struct {
             uint32_t pos[SPCAP];
@@ -72,6 +75,29 @@ struct HubLds {
         int32_t dl[HCH];
     } b;
 };
+
+// Lower bound of x in row[0, n) found by the whole wavefront: each round the
+// 64 lanes probe the last entry of 64 equal buckets, so a search over n
+// entries takes about log_64(n) + 1 dependent loads instead of log_2(n).
+__device__ uint32_t wave_lower_bound(const uint32_t *__restrict__ row, uint32_t n, uint32_t x)
+{
+    const int l = lane_id();
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > (uint32_t)WAVE) {
+        const uint32_t step = (hi - lo + WAVE - 1) / WAVE;
+        uint32_t p = lo + (uint32_t)(l + 1) * step - 1;
+        if (p > hi - 1) p = hi - 1;
+        const uint64_t m = ballot(row[p] >= x);
+        if (m == 0) return hi;
+        const int f = first_lane(m);
+        const uint32_t nhi = lo + (uint32_t)(f + 1) * step;
+        lo = lo + (uint32_t)f * step;
+        hi = nhi < hi ? nhi : hi;
+    }
+    const uint32_t p = lo + l;
+    const uint64_t m = ballot(p < hi && row[p] >= x);
+    return m ? lo + first_lane(m) : hi;
+}
 
 // The state of lane o in scalar registers.
 __device__ __forceinline__ WS bcast(const WS &s, int o)
@@ -196,108 +222,124 @@ __device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, uin
 }
 
 // ------------------------------------------------------------------ hubs
-// Stages N(v)[j0, j0+cnt) in LDS and flags the members of N(t), streaming
-// N(t) from ypos (advanced past every value <= the chunk's last entry).  The
-// chunk and the first block of N(t) are loaded together.  Returns the number
-// of flagged entries.
-__device__ uint32_t dense_flags(const Exec &E, const WS &st, HubLds &L, uint64_t j0, uint32_t cnt, uint64_t &ypos)
+// Flags the tile entries equal to a block of NB x 64 entries of N(t) loaded
+// from ypos; returns how many block entries lie in the tile's value range
+// (they form a prefix of the block, N(t) being sorted).
+template <int NB>
+__device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB], uint32_t ypos, uint32_t td,
+                                               uint32_t cnt, uint32_t xlast)
 {
     const int l = lane_id();
-    const uint32_t *__restrict__ adj = E.g.adj;
-    const uint64_t td = st.td;
-    uint32_t xv[HEPL], y[YB];
+    uint32_t nin = 0;
 #pragma unroll
-    for (int e = 0; e < HEPL; ++e) {
+    for (int b = 0; b < NB; ++b) {
+        const bool in = ypos + b * WAVE + l < td && y[b] <= xlast;
+        nin += __popcll(ballot(in));
+        if (in) {  // branchless search over the padded tile: pos = entries below y
+            uint32_t pos = 0;
+#pragma unroll
+            for (uint32_t step = TX / 2; step >= 1; step >>= 1)
+                if (L.a.d.xs[pos + step - 1] < y[b]) pos += step;
+            if (pos < cnt && L.a.d.xs[pos] == y[b]) L.a.d.flag[pos] = 1;
+        }
+    }
+    return nin;
+}
+
+// Stages N(v)[j0, j0+cnt) (cnt <= TX) in LDS and flags the members of N(t),
+// streaming N(t) from ypos (advanced past every value <= the tile's last
+// entry).  The tile and a first, small block of N(t) are loaded together
+// (most windows are short); a block consumed entirely is followed by
+// full-size blocks.  Returns the number of flagged entries.
+__device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y, uint32_t td,
+                                HubLds &L, uint32_t j0, uint32_t cnt, uint32_t &ypos)
+{
+    const int l = lane_id();
+    uint32_t xv[XPL], y0[YFIRST];
+#pragma unroll
+    for (int e = 0; e < XPL; ++e) {
         const uint32_t i = e * WAVE + l;
-        xv[e] = i < cnt ? adj[st.vo + j0 + i] : 0xFFFFFFFFu;
+        xv[e] = i < cnt ? X[j0 + i] : 0xFFFFFFFFu;
     }
 #pragma unroll
-    for (int b = 0; b < YB; ++b) {
-        const uint64_t idx = ypos + b * WAVE + l;
-        y[b] = idx < td ? adj[st.to + idx] : 0xFFFFFFFFu;
+    for (int b = 0; b < YFIRST; ++b) {
+        const uint32_t idx = ypos + b * WAVE + l;
+        y0[b] = idx < td ? Y[idx] : 0xFFFFFFFFu;
     }
 #pragma unroll
-    for (int e = 0; e < HEPL; ++e) {
+    for (int e = 0; e < XPL; ++e) {
         L.a.d.xs[e * WAVE + l] = xv[e];
         L.a.d.flag[e * WAVE + l] = 0;
     }
     wave_lds_sync();
     const uint32_t xlast = L.a.d.xs[cnt - 1];
-    for (;;) {
-        uint32_t nin = 0;
+    uint32_t nin = flag_block<YFIRST>(L, y0, ypos, td, cnt, xlast);
+    ypos += nin;
+    if (nin == YFIRST * WAVE) {
+        while (ypos < td) {
+            uint32_t y[YPL];
 #pragma unroll
-        for (int b = 0; b < YB; ++b) {
-            const bool in = ypos + b * WAVE + l < td && y[b] <= xlast;
-            nin += __popcll(ballot(in));
-            if (in) {
-                uint32_t lo = 0, hi = cnt;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (L.a.d.xs[mid] < y[b]) lo = mid + 1;
-                    else hi = mid;
-                }
-                if (lo < cnt && L.a.d.xs[lo] == y[b]) L.a.d.flag[lo] = 1;
+            for (int b = 0; b < YPL; ++b) {
+                const uint32_t idx = ypos + b * WAVE + l;
+                y[b] = idx < td ? Y[idx] : 0xFFFFFFFFu;
             }
-        }
-        ypos += nin;
-        if (nin < YB * WAVE || ypos >= td) break;
-#pragma unroll
-        for (int b = 0; b < YB; ++b) {
-            const uint64_t idx = ypos + b * WAVE + l;
-            y[b] = idx < td ? adj[st.to + idx] : 0xFFFFFFFFu;
+            nin = flag_block<YPL>(L, y, ypos, td, cnt, xlast);
+            ypos += nin;
+            if (nin < YPL * WAVE) break;
         }
     }
     wave_lds_sync();
     uint32_t c = 0;
 #pragma unroll
-    for (int e = 0; e < HEPL; ++e) c += L.a.d.flag[e * WAVE + l];
+    for (int e = 0; e < XPL; ++e) c += L.a.d.flag[e * WAVE + l];
     return wave_sum32(c);
 }
 
-__device__ __forceinline__ uint64_t dense_pi(const Exec &E, const JobCtx &J, const WS &st, const HubLds &L,
-                                             uint64_t j0, uint32_t i)
+// pi of entry j0+i of a tile (weights from W, or 1).
+__device__ __forceinline__ uint64_t dense_pi(const uint16_t *__restrict__ W, const JobCtx &J, uint32_t pos_t,
+                                             const HubLds &L, uint32_t j0, uint32_t i)
 {
-    const uint64_t w = E.g.wt ? E.g.wt[st.vo + j0 + i] : 1u;
-    const uint32_t m = (j0 + i == st.pos_t) ? J.A_ret : (L.a.d.flag[i] ? A_COM : J.A_out);
+    const uint64_t w = W ? W[j0 + i] : 1u;
+    const uint32_t m = (j0 + i == pos_t) ? J.A_ret : (L.a.d.flag[i] ? A_COM : J.A_out);
     return w * m;
 }
 
-__device__ uint64_t dense_chunk_sum(const Exec &E, const JobCtx &J, const WS &st, const HubLds &L, uint64_t j0,
-                                    uint32_t cnt)
+__device__ uint64_t dense_chunk_sum(const uint16_t *__restrict__ W, const JobCtx &J, uint32_t pos_t,
+                                    const HubLds &L, uint32_t j0, uint32_t cnt)
 {
     const int l = lane_id();
     uint64_t s = 0;
 #pragma unroll
-    for (int e = 0; e < HEPL; ++e) {
+    for (int e = 0; e < XPL; ++e) {
         const uint32_t i = e * WAVE + l;
-        if (i < cnt) s += dense_pi(E, J, st, L, j0, i);
+        if (i < cnt) s += dense_pi(W, J, pos_t, L, j0, i);
     }
     return wave_sum(s);
 }
 
-// First index of the chunk whose running prefix (base + partial) exceeds r,
-// or SENT (base then holds the prefix after the chunk).
-__device__ uint32_t dense_chunk_locate(const Exec &E, const JobCtx &J, const WS &st, const HubLds &L, uint64_t j0,
-                                       uint32_t cnt, uint64_t &base, uint64_t r)
+// First index of the tile whose running prefix (base + partial) exceeds r,
+// or SENT (base then holds the prefix after the tile).
+__device__ uint32_t dense_chunk_locate(const uint16_t *__restrict__ W, const JobCtx &J, uint32_t pos_t,
+                                       const HubLds &L, uint32_t j0, uint32_t cnt, uint64_t &base, uint64_t r)
 {
     const int l = lane_id();
 #pragma unroll 1
-    for (int e = 0; e < HEPL; ++e) {
+    for (int e = 0; e < XPL; ++e) {
         const uint32_t i = e * WAVE + l;
-        const uint64_t pi = i < cnt ? dense_pi(E, J, st, L, j0, i) : 0;
+        const uint64_t pi = i < cnt ? dense_pi(W, J, pos_t, L, j0, i) : 0;
         const uint64_t inc = wave_incl_scan(pi);
         const uint64_t m = ballot(i < cnt && base + inc > r);
-        if (m) return (uint32_t)(j0 + e * WAVE + first_lane(m));
+        if (m) return j0 + e * WAVE + first_lane(m);
         base += lane_val64(inc, WAVE - 1);
     }
     return SENT;
 }
 
 // Sum of pi over N(v)[j0, j0+len) of an unweighted row with c members of N(t).
-__device__ __forceinline__ uint64_t seg_pi(const JobCtx &J, const WS &st, uint64_t j0, uint64_t len, uint32_t c)
+__device__ __forceinline__ uint64_t seg_pi(const JobCtx &J, uint32_t pos_t, uint32_t j0, uint32_t len, uint32_t c)
 {
     uint64_t s = (uint64_t)J.A_out * len + (uint64_t)((int64_t)((int32_t)A_COM - (int32_t)J.A_out) * (int64_t)c);
-    if (st.pos_t >= j0 && st.pos_t < j0 + len) s += (uint64_t)((int64_t)J.A_ret - (int64_t)J.A_out);
+    if (pos_t >= j0 && pos_t - j0 < len) s += (uint64_t)((int64_t)J.A_ret - (int64_t)J.A_out);
     return s;
 }
 
@@ -308,60 +350,62 @@ __device__ __forceinline__ uint64_t seg_pi(const JobCtx &J, const WS &st, uint64
 __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, uint64_t R1)
 {
     const int l = lane_id();
-    const uint64_t dv = st.vd;
-    const uint64_t nsub = (dv + HCH - 1) / HCH;
-    const uint64_t G = (nsub + NSUPER - 1) / NSUPER;   // sub-chunks per segment
-    const uint64_t nsup = (nsub + G - 1) / G;
-    const uint64_t seglen = G * HCH;
-    const bool weighted = E.g.wt != nullptr;
+    const uint32_t *__restrict__ X = E.g.adj + st.vo;
+    const uint32_t *__restrict__ Y = E.g.adj + st.to;
+    const uint16_t *__restrict__ W = E.g.wt ? E.g.wt + st.vo : nullptr;
+    const uint32_t dv = st.vd, td = st.td, pos_t = st.pos_t;
+    const uint32_t nsub = (dv + TX - 1) / TX;
+    const uint32_t G = (nsub + NSUPER - 1) / NSUPER;  // tiles per segment
+    const uint32_t nsup = (nsub + G - 1) / G;
+    const uint32_t seglen = G * TX;
     uint16_t *row = nullptr;
-    if (E.g.memo && !weighted && st.pos_t != SENT)
-        row = E.g.memo + (E.g.hbase[st.v] + st.pos_t) * (uint64_t)MEMO_SEGS;
+    if (E.g.memo && !W && pos_t != SENT && dv > E.g.d_rule)
+        row = E.g.memo + (E.g.hbase[st.v] + pos_t) * (uint64_t)MEMO_SEGS;
     bool warm = false;
     uint32_t known = 1;
     if (row) {
-        if ((uint64_t)l < nsup) known = row[l];
+        if ((uint32_t)l < nsup) known = row[l];
         warm = ballot(known == 0) == 0;
     }
     uint64_t S;
     if (warm) {
         uint64_t pi = 0;
-        if ((uint64_t)l < nsup) {
-            const uint64_t a = l * seglen;
-            const uint64_t len = std::min(seglen, dv - a);
-            pi = seg_pi(J, st, a, len, known - 1);
+        if ((uint32_t)l < nsup) {
+            const uint32_t a = l * seglen;
+            pi = seg_pi(J, pos_t, a, dv - a < seglen ? dv - a : seglen, known - 1);
             L.b.csum[l] = pi;
         }
         S = wave_sum(pi);
     } else {
-        uint64_t ypos = st.td ? lower_bound_g(E.g.adj, st.to, st.to + st.td, E.g.adj[st.vo]) - st.to : 0;
+        uint32_t ypos = td ? wave_lower_bound(Y, td, X[0]) : 0;
         uint32_t mine = 0;
         S = 0;
-        for (uint64_t sp = 0; sp < nsup; ++sp) {
+        for (uint32_t sp = 0; sp < nsup; ++sp) {
             uint64_t sum = 0;
             uint32_t csp = 0;
-            const uint64_t sub_end = std::min(nsub, (sp + 1) * G);
-            for (uint64_t sub = sp * G; sub < sub_end; ++sub) {
-                const uint64_t j0 = sub * HCH;
-                const uint32_t cnt = (uint32_t)std::min<uint64_t>(HCH, dv - j0);
-                const uint32_t c = dense_flags(E, st, L, j0, cnt, ypos);
-                sum += weighted ? dense_chunk_sum(E, J, st, L, j0, cnt) : seg_pi(J, st, j0, cnt, c);
+            const uint32_t sub_end = nsub < (sp + 1) * G ? nsub : (sp + 1) * G;
+            for (uint32_t sub = sp * G; sub < sub_end; ++sub) {
+                const uint32_t j0 = sub * TX;
+                const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
+                const uint32_t c = dense_flags(X, Y, td, L, j0, cnt, ypos);
+                sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, c);
                 csp += c;
                 wave_lds_sync();
             }
             if (l == 0) L.b.csum[sp] = sum;
-            if ((uint64_t)l == sp) mine = csp;
+            if ((uint32_t)l == sp) mine = csp;
             S += sum;
         }
-        if (row && (uint64_t)l < nsup) __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
+        if (row && (uint32_t)l < nsup) __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
     }
     wave_lds_sync();
     const uint64_t r = hi64(R1, S);
-    uint64_t base = 0, spx = nsup - 1;
+    uint64_t base;
+    uint32_t spx = nsup - 1;
     {
-        const uint64_t c = (uint64_t)l < nsup ? L.b.csum[l] : 0;
+        const uint64_t c = (uint32_t)l < nsup ? L.b.csum[l] : 0;
         const uint64_t inc = wave_incl_scan(c);
-        const uint64_t m = ballot((uint64_t)l < nsup && inc > r);
+        const uint64_t m = ballot((uint32_t)l < nsup && inc > r);
         if (m) {
             const int f = first_lane(m);
             spx = f;
@@ -371,18 +415,18 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         }
     }
     wave_lds_sync();
-    const uint64_t x0 = spx * seglen;
-    uint64_t ypos = st.td ? lower_bound_g(E.g.adj, st.to, st.to + st.td, E.g.adj[st.vo + x0]) - st.to : 0;
-    const uint64_t sub_end = std::min(nsub, (spx + 1) * G);
-    for (uint64_t sub = spx * G; sub < sub_end; ++sub) {
-        const uint64_t j0 = sub * HCH;
-        const uint32_t cnt = (uint32_t)std::min<uint64_t>(HCH, dv - j0);
-        dense_flags(E, st, L, j0, cnt, ypos);
-        const uint32_t j = dense_chunk_locate(E, J, st, L, j0, cnt, base, r);
+    const uint32_t x0 = spx * seglen;
+    uint32_t ypos = td ? wave_lower_bound(Y, td, X[x0]) : 0;
+    const uint32_t sub_end = nsub < (spx + 1) * G ? nsub : (spx + 1) * G;
+    for (uint32_t sub = spx * G; sub < sub_end; ++sub) {
+        const uint32_t j0 = sub * TX;
+        const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
+        dense_flags(X, Y, td, L, j0, cnt, ypos);
+        const uint32_t j = dense_chunk_locate(W, J, pos_t, L, j0, cnt, base, r);
         wave_lds_sync();
         if (j != SENT) return j;
     }
-    return (uint32_t)(dv - 1);  // not reached: the last prefix equals S > r
+    return dv - 1;  // not reached: the last prefix equals S > r
 }
 
 // Weighted scan with specials: pi_j = m0 * w_j + delta_j, the deltas of the
@@ -432,15 +476,29 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
     const int l = lane_id();
     const uint32_t *__restrict__ adj = E.g.adj;
     const uint64_t vo = st.vo, dv = st.vd;
+    // 64 pivots (the last entry of 64 equal buckets of N(v)) in LDS; each
+    // search starts inside the one bucket that can hold its value
+    const uint64_t bsz = (dv + WAVE - 1) / WAVE;
+    uint32_t *piv = (uint32_t *)L.b.dl;
+    piv[l] = adj[std::min<uint64_t>(vo + (uint64_t)(l + 1) * bsz - 1, vo + dv - 1)];
+    wave_lds_sync();
     uint32_t c = 0;
     for (uint32_t b = 0; b < st.td; b += WAVE) {
         const uint32_t idx = b + l;
         const bool valid = idx < st.td;
         bool found = false;
         uint64_t p = 0;
+        const uint32_t y = valid ? adj[st.to + idx] : 0xFFFFFFFFu;
+        // bucket = number of pivots below y
+        uint32_t k = 0;
+#pragma unroll
+        for (uint32_t step = WAVE / 2; step >= 1; step >>= 1)
+            if (piv[k + step - 1] < y) k += step;
+        if (k == WAVE - 1 && piv[WAVE - 1] < y) k = WAVE;
         if (valid) {
-            const uint32_t y = adj[st.to + idx];
-            p = lower_bound_g(adj, vo, vo + dv, y);
+            const uint64_t lo = vo + (uint64_t)k * bsz;
+            const uint64_t hi = std::min<uint64_t>(lo + bsz, vo + dv);
+            p = lo < vo + dv ? lower_bound_g(adj, lo, hi, y) : vo + dv;
             found = p < vo + dv && adj[p] == y;
         }
         const uint64_t m = ballot(found);
@@ -588,7 +646,9 @@ struct OneJob {
     JobCtx c;
     const uint32_t *starts;
     uint32_t n;
+    uint32_t *cur;
     __device__ uint32_t total() const { return n; }
+    __device__ uint32_t *cursor() const { return cur; }
     __device__ void locate(uint32_t g, uint32_t &job, uint32_t &i) const
     {
         job = 0;
@@ -604,6 +664,7 @@ struct OneJob {
 struct JobTable {
     const TableHdr *hdr;
     __device__ uint32_t total() const { return hdr->total; }
+    __device__ uint32_t *cursor() const { return const_cast<uint32_t *>(&hdr->cursor); }
     __device__ void locate(uint32_t g, uint32_t &job, uint32_t &i) const
     {
         uint32_t lo = 0, hi = hdr->njobs;  // last job with jstart <= g
@@ -622,82 +683,164 @@ struct JobTable {
 // ---------------------------------------------------------- persistent
 constexpr int PBLOCK = 256;
 constexpr int THREAD_ITERS = 8;
+constexpr int POOL = 256;  // walks a wavefront claims per atomic
+
+// Walk slot of one lane, kept in LDS between the thread and wave phases so
+// that neither phase holds the other's registers.
+struct Slot {
+    uint32_t job, i, s, v, t, pos_t, jprev;
+    uint32_t flags;  // bit 0: live, bit 1: pending wave/hub move, bit 2: after a_cap rejections
+};
+enum : uint32_t { SL_LIVE = 1, SL_PEND = 2, SL_CAP = 4 };
+
+__device__ __forceinline__ void slot_to_ws(const Exec &E, const Slot &q, WS &st)
+{
+    st.job = q.job;
+    st.i = q.i;
+    st.s = q.s;
+    st.t = q.t;
+    st.pos_t = q.pos_t;
+    st.jprev = q.jprev;
+    load_v(E, st, q.v);
+    if (q.s > 0) {
+        const VRec r = E.g.vrec[q.t];
+        st.to = r.off;
+        st.td = r.deg;
+    } else {
+        st.to = 0;
+        st.td = 0;
+    }
+}
+
+__device__ __forceinline__ void ws_to_slot(const WS &st, uint32_t flags, Slot &q)
+{
+    q.job = st.job;
+    q.i = st.i;
+    q.s = st.s;
+    q.v = st.v;
+    q.t = st.t;
+    q.pos_t = st.pos_t;
+    q.jprev = st.jprev;
+    q.flags = flags;
+}
 
 template <class Src, bool WALKS, bool COUNTS>
 __global__ __launch_bounds__(PBLOCK) void k_persistent(Exec E, Src S)
 {
     __shared__ HubLds lds[PBLOCK / WAVE];
+    __shared__ Slot slots[PBLOCK / WAVE][WAVE];
     HubLds &L = lds[threadIdx.x / WAVE];
+    Slot *sl = slots[threadIdx.x / WAVE];
     const int l = lane_id();
-    const uint64_t gw = (uint64_t)blockIdx.x * (PBLOCK / WAVE) + threadIdx.x / WAVE;
-    const uint64_t stride = (uint64_t)gridDim.x * PBLOCK;
     const uint32_t total = S.total();
-    uint64_t next = gw * WAVE + l;
-    WS st{};
-    bool live = false, pend = false;
-    uint32_t pk = 0;
-    uint64_t csum = 0;
     const uint32_t tw = E.t_wave < E.g.d_rule ? E.t_wave : E.g.d_rule;
+    uint32_t pool_next = 0, pool_end = 0;  // walks this wavefront has claimed but not started
+    bool exhausted = false;
+    uint64_t csum = 0;
+    sl[l].flags = 0;
     for (;;) {
-        while (!live && next < total) {
-            uint32_t job, i;
-            S.locate((uint32_t)next, job, i);
-            const JobCtx J = S.ctx(job);
-            live = start_walk<WALKS, COUNTS>(E, J, job, i, S.start(job, i), st, csum);
-            pend = false;
-            next += stride;
-        }
-        if (ballot(live) == 0) break;
-        // thread class
-        for (int it = 0; it < THREAD_ITERS; ++it) {
-            if (live && !pend && st.vd > tw) {
-                pend = true;
-                pk = 0;
-            }
-            const bool can = live && !pend;
-            if (ballot(can) == 0) break;
-            if (can) {
-                const JobCtx J = S.ctx(st.job);
-                uint32_t j;
-                if (thread_reject(E, J, st, j)) {
-                    uint32_t x, rev;
-                    resolve(E, st, j, x, rev);
-                    emit<WALKS, COUNTS>(J, st.i, st.s + 1, x, csum);
-                    advance(E, st, j, x, rev);
-                    if (st.s == J.L || st.vd == 0) {
-                        fill_tail_lane<WALKS>(J, st.i, st.s);
-                        live = false;
+        // refill and thread class: the lane's own walk
+        {
+            Slot q = sl[l];
+            WS st;
+            bool live = q.flags & SL_LIVE;
+            bool pend = q.flags & SL_PEND;
+            uint32_t cap = q.flags & SL_CAP;
+            if (live) slot_to_ws(E, q, st);
+            // idle lanes start walks claimed from the global counter, POOL at a time
+            for (;;) {
+                const uint64_t m = ballot(!live);
+                if (m == 0) break;
+                if (pool_next >= pool_end) {
+                    if (exhausted) break;
+                    uint32_t b = 0;
+                    if (l == 0) b = atomicAdd(S.cursor(), (uint32_t)POOL);
+                    b = uni(b);
+                    if (b >= total) {
+                        exhausted = true;
+                        break;
                     }
-                } else {
-                    pend = true;
-                    pk = E.g.a_cap;
+                    pool_next = b;
+                    pool_end = total - b < (uint32_t)POOL ? total : b + POOL;
+                }
+                const uint32_t avail = pool_end - pool_next;
+                const uint32_t r = __popcll(m & lanemask_lt());
+                if (!live && r < avail) {
+                    uint32_t job, i;
+                    S.locate(pool_next + r, job, i);
+                    const JobCtx J = S.ctx(job);
+                    live = start_walk<WALKS, COUNTS>(E, J, job, i, S.start(job, i), st, csum);
+                    pend = false;
+                    cap = 0;
+                }
+                const uint32_t took = __popcll(m);
+                pool_next += took < avail ? took : avail;
+            }
+            if (ballot(live) == 0) break;
+            for (int it = 0; it < THREAD_ITERS; ++it) {
+                if (live && !pend && st.vd > tw) pend = true;
+                const bool can = live && !pend;
+                if (ballot(can) == 0) break;
+                if (can) {
+                    const JobCtx J = S.ctx(st.job);
+                    uint32_t j;
+                    if (thread_reject(E, J, st, j)) {
+                        uint32_t x, rev;
+                        resolve(E, st, j, x, rev);
+                        emit<WALKS, COUNTS>(J, st.i, st.s + 1, x, csum);
+                        advance(E, st, j, x, rev);
+                        if (st.s == J.L || st.vd == 0) {
+                            fill_tail_lane<WALKS>(J, st.i, st.s);
+                            live = false;
+                        }
+                    } else {
+                        pend = true;
+                        cap = SL_CAP;
+                    }
                 }
             }
+            if (live && !pend) pend = st.vd > tw;
+            if (live) ws_to_slot(st, SL_LIVE | (pend ? SL_PEND : 0) | cap, q);
+            else q.flags = 0;
+            sl[l] = q;
         }
-        if (live && !pend) {
-            pend = st.vd > tw;
-            pk = 0;
-        }
-        // wave and hub classes, one pending walk at a time
-        uint64_t pm = ballot(live && pend);
+        wave_lds_sync();
+        // wave and hub classes, one pending walk at a time, state in scalars
+        uint64_t pm = ballot((sl[l].flags & (SL_LIVE | SL_PEND)) == (SL_LIVE | SL_PEND));
         while (pm) {
             const int o = first_lane(pm);
             pm &= pm - 1;
-            WS w = bcast(st, o);
-            w.job = __builtin_amdgcn_readfirstlane(w.job);
+            Slot q;
+            q.job = uni(sl[o].job);
+            q.i = uni(sl[o].i);
+            q.s = uni(sl[o].s);
+            q.v = uni(sl[o].v);
+            q.t = uni(sl[o].t);
+            q.pos_t = uni(sl[o].pos_t);
+            q.jprev = uni(sl[o].jprev);
+            q.flags = uni(sl[o].flags);
+            WS w;
+            slot_to_ws(E, q, w);
+            w = uniform_ws(w);
             const JobCtx J = S.ctx(w.job);
-            uint32_t k = lane_val(pk, o);
+            bool capped = q.flags & SL_CAP;
             bool alive = true;
             for (;;) {
-                uint32_t j;
-                if (k == E.g.a_cap) j = wave_inverse_cdf(E, J, w, k, L);
-                else if (w.vd > E.g.d_rule) j = wave_inverse_cdf(E, J, w, 0, L);
-                else if (!wave_reject(E, J, w, j)) j = wave_inverse_cdf(E, J, w, E.g.a_cap, L);
+                uint32_t j = 0, kidx = capped ? E.g.a_cap : 0u;
+                bool icdf = capped || w.vd > E.g.d_rule;
+                if (!icdf && !wave_reject(E, J, w, j)) {
+                    icdf = true;
+                    kidx = E.g.a_cap;
+                }
+                if (icdf) j = wave_inverse_cdf(E, J, w, kidx, L);
                 uint32_t x, rev;
                 resolve(E, w, j, x, rev);
+                x = uni(x);
+                rev = uni(rev);
                 if (l == 0) emit<WALKS, COUNTS>(J, w.i, w.s + 1, x, csum);
                 advance(E, w, j, x, rev);
-                k = 0;
+                w = uniform_ws(w);
+                capped = false;
                 if (w.s == J.L || w.vd == 0) {
                     fill_tail_wave<WALKS>(J, w.i, w.s);
                     alive = false;
@@ -705,11 +848,14 @@ __global__ __launch_bounds__(PBLOCK) void k_persistent(Exec E, Src S)
                 }
                 if (w.vd <= tw) break;
             }
+            wave_lds_sync();
             if (l == o) {
-                st = w;
-                live = alive;
-                pend = false;
+                Slot r;
+                if (alive) ws_to_slot(w, SL_LIVE, r);
+                else r.flags = 0;
+                sl[o] = r;
             }
+            wave_lds_sync();
         }
     }
     if (COUNTS) {
@@ -818,15 +964,18 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
 // One workgroup-resident wavefront per hub move of this superstep.
 template <bool WALKS, bool COUNTS>
 __global__ __launch_bounds__(256, 4) void k_plain_hub(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
-                                                   const uint32_t *__restrict__ hubq, const uint32_t *__restrict__ hubn)
+                                                      const uint32_t *__restrict__ hubq, const uint32_t *__restrict__ hubn,
+                                                      uint32_t *__restrict__ hubd)
 {
     __shared__ HubLds lds[256 / WAVE];
     HubLds &L = lds[threadIdx.x / WAVE];
-    const uint32_t gw = uni(blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE);
-    const uint32_t nw = gridDim.x * (256 / WAVE);
     const uint32_t n = *hubn;
     uint64_t csum = 0;
-    for (uint32_t q = gw; q < n; q += nw) {
+    for (;;) {
+        uint32_t q = 0;
+        if (lane_id() == 0) q = atomicAdd(hubd, 1u);
+        q = uni(q);
+        if (q >= n) break;
         const uint32_t item = uni(hubq[q]);
         const uint32_t i = item & 0x7FFFFFFFu;
         const uint32_t kidx = (item & 0x80000000u) ? E.g.a_cap : 0u;
@@ -879,7 +1028,7 @@ size_t plain_ws(uint32_t n_starts, uint32_t L)
     Carver c(nullptr, 0);
     c.take<uint4>(n_starts ? n_starts : 1);
     c.take<uint32_t>(n_starts ? n_starts : 1);
-    c.take<uint32_t>((uint64_t)L + 1);
+    c.take<uint32_t>(2 * ((uint64_t)L + 1));
     return c.total();
 }
 
@@ -899,6 +1048,7 @@ uint32_t persistent_blocks(const n2v_exec_opts &o, int dev, uint64_t walks)
 template <bool W, bool C>
 int launch_persistent(const Exec &E, const OneJob &S, const n2v_exec_opts &o, int dev, hipStream_t st)
 {
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, S.cur, 1u);
     hipLaunchKernelGGL((k_persistent<OneJob, W, C>), dim3(persistent_blocks(o, dev, S.n)), dim3(PBLOCK), 0, st, E, S);
     N2V_HIP(hipGetLastError());
     return N2V_OK;
@@ -910,9 +1060,10 @@ int launch_plain(const Exec &E, const OneJob &S, void *ws, int dev, hipStream_t 
     Carver c(ws, (size_t)-1);
     uint4 *state = c.take<uint4>(S.n ? S.n : 1);
     uint32_t *hubq = c.take<uint32_t>(S.n ? S.n : 1);
-    uint32_t *hubn = c.take<uint32_t>((uint64_t)S.c.L + 1);
+    uint32_t *hubn = c.take<uint32_t>(2 * ((uint64_t)S.c.L + 1));  // per superstep: enqueued, dequeued
+    uint32_t *hubd = hubn + S.c.L + 1;
     const uint32_t blocks = (S.n + 255) / 256;
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, hubn, S.c.L + 1);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, hubn, 2 * (S.c.L + 1));
     hipLaunchKernelGGL((k_plain_init<W, C>), dim3(blocks), dim3(256), 0, st, E, S, state);
     N2V_HIP(hipGetLastError());
     DevInfo &d = dev_info(dev);
@@ -920,7 +1071,7 @@ int launch_plain(const Exec &E, const OneJob &S, void *ws, int dev, hipStream_t 
     for (uint32_t s = 0; s < S.c.L; ++s) {
         hipLaunchKernelGGL((k_plain_step<W, C>), dim3(blocks), dim3(256), 0, st, E, S, s, state, hubq, hubn + s);
         hipLaunchKernelGGL((k_plain_hub<W, C>), dim3(hub_blocks), dim3(256), 0, st, E, S, s, state, hubq,
-                           (const uint32_t *)(hubn + s));
+                           (const uint32_t *)(hubn + s), hubd + s);
     }
     N2V_HIP(hipGetLastError());
     return N2V_OK;
@@ -947,6 +1098,8 @@ int walk_multipliers(float p, float q, uint32_t *A_ret, uint32_t *A_out)
 void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E)
 {
     E->g = g->dg;
+    const uint32_t slot = __atomic_fetch_add(&const_cast<n2v_graph *>(g)->next_cursor, 1u, __ATOMIC_RELAXED);
+    E->cursor = g->dg.cursors + (uint64_t)(slot % CURSOR_SLOTS) * CURSOR_STRIDE;
     if (!o.memo) E->g.memo = nullptr;
     E->t_wave = o.t_wave;
     E->t_sparse = o.t_sparse;
@@ -975,6 +1128,7 @@ int launch_one(const Exec &E, const JobCtx &c, const uint32_t *starts, uint32_t 
     S.c = c;
     S.starts = starts;
     S.n = n;
+    S.cur = E.cursor;
     return launch_persistent<true, false>(E, S, o, dev, st);
 }
 
@@ -1045,6 +1199,7 @@ extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t 
     S.c.A_out = A_out;
     S.starts = starts;
     S.n = n_starts;
+    S.cur = E.cursor;
     hipStream_t st = (hipStream_t)stream;
     if (E.g.memo) {  // sketches are rebuilt within each call
         const uint64_t words = (uint64_t)g->memo_bytes / 4;

@@ -13,6 +13,7 @@ struct Exec {
     uint32_t t_wave;        // rejection moves at degree > t_wave run wave-cooperatively
     uint32_t t_sparse;      // largest deg(t) for the sparse hub path
     uint32_t sparse_ratio;  // cost weight of one search against streaming
+    uint32_t *cursor;       // next unassigned walk of a single-job launch (zeroed before it)
 };
 
 // Parameters of one walk job: a set of walks with the same (L, p, q, seed).
@@ -40,6 +41,7 @@ constexpr uint32_t MAX_TABLE_JOBS = 256;
 struct alignas(256) TableHdr {
     uint32_t njobs;
     uint32_t total;                         // sum of the job sizes
+    uint32_t cursor;                        // next unassigned walk (0 in the host copy)
     uint32_t jstart[MAX_TABLE_JOBS + 1];    // prefix sums of the job sizes
     JobRec jobs[MAX_TABLE_JOBS];
 };
