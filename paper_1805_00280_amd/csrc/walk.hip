@@ -963,7 +963,7 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
 
 // One workgroup-resident wavefront per hub move of this superstep.
 template <bool WALKS, bool COUNTS>
-__global__ __launch_bounds__(256, 4) void k_plain_hub(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
+__global__ __launch_bounds__(256, 6) void k_plain_hub(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
                                                       const uint32_t *__restrict__ hubq, const uint32_t *__restrict__ hubn,
                                                       uint32_t *__restrict__ hubd)
 {
