@@ -398,7 +398,8 @@ _hip = None
 def _hip_runtime():
     global _hip
     if _hip is None:
-        _hip = C.CDLL("libamdhip64.so")
+        # the runtime torch already loaded (same soname), never a second copy
+        _hip = C.CDLL("libamdhip64.so.7")
         _hip.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
         _hip.hipMemcpyAsync.restype = C.c_int
     return _hip

@@ -1,0 +1,116 @@
+"""Continuous-batching server: every result equals the oracle's walk of the
+same request (walk ids 0.., the request's own seed), alone or in any mix."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1805_00280_amd as P
+from gpuhelp import gpu_graph_from_oracle, gpu_walk, oracle_rmat, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+PQ = [0.25, 0.5, 1.0, 2.0, 4.0]
+
+
+@pytest.fixture(scope="module")
+def graph():
+    torch_cuda()
+    og = oracle_rmat(13, 16, 0.57, 0.19, 0.19, 13, False)
+    return og, gpu_graph_from_oracle(og, d_rule=64)
+
+
+def requests(n_nodes, count, seed, max_size=5000):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        size = int(rng.integers(1, max_size))
+        out.append(dict(starts=rng.integers(0, n_nodes, size=size).astype(np.uint32),
+                        L=int(rng.choice([5, 20, 40])), p=float(rng.choice(PQ)), q=float(rng.choice(PQ)),
+                        seed=int(rng.integers(0, 2**62))))
+    return out
+
+
+def wait_all(srv, tickets, timeout=60):
+    t0 = time.time()
+    done = {}
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = r
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.001)
+    return done
+
+
+def test_mix_equals_oracle_and_alone(graph):
+    og, g = graph
+    reqs = requests(og.n, 40, 1)
+    srv = P.Server(g, pool_bytes=64 << 20, chunk_walks=700, max_inflight=16)
+    tickets = [srv.submit(r["starts"], r["L"], r["p"], r["q"], r["seed"]) for r in reqs]
+    done = wait_all(srv, tickets)
+    for r, t in zip(reqs, tickets):
+        got = srv.result_tensor(done[t])
+        want = O.walk(og, r["starts"], r["L"], r["p"], r["q"], r["seed"], d_rule=64, nthreads=16)["out"]
+        assert np.array_equal(got, want)
+        alone = gpu_walk(g, r["starts"], r["L"], r["p"], r["q"], r["seed"])
+        assert np.array_equal(got, alone)
+        res = done[t]
+        assert res.submit_ns <= res.start_ns <= res.done_ns
+        srv.release(t)
+    assert srv.stats() == (0, 0, 0)
+    srv.close()
+
+
+def test_tiny_pool_queues_and_admits_as_memory_frees(graph):
+    og, g = graph
+    # room for about two requests at a time: the rest wait for releases
+    reqs = [dict(starts=np.arange(i * 100, i * 100 + 3000, dtype=np.uint32) % og.n, L=40, p=0.5, q=2.0, seed=i)
+            for i in range(8)]
+    per = 3000 * 4 + 3000 * 41 * 4
+    srv = P.Server(g, pool_bytes=2 * (per + 4096) + 2 * 2**20, chunk_walks=512)
+    tickets = [srv.submit(r["starts"], r["L"], r["p"], r["q"], r["seed"]) for r in reqs]
+    say(f"[server] stats after submit {srv.stats()}")
+    finished = 0
+    t0 = time.time()
+    while finished < len(tickets):
+        for i, t in enumerate(tickets):
+            if t is None:
+                continue
+            r = srv.poll(t)
+            if r is not None:
+                got = srv.result_tensor(r)
+                want = O.walk(og, reqs[i]["starts"], 40, 0.5, 2.0, reqs[i]["seed"], d_rule=64)["out"]
+                assert np.array_equal(got, want)
+                srv.release(t)
+                tickets[i] = None
+                finished += 1
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    srv.close()
+
+
+def test_errors(graph):
+    og, g = graph
+    srv = P.Server(g, pool_bytes=8 << 20)
+    with pytest.raises(P.N2VError) as e:
+        srv.submit(np.zeros(200000, dtype=np.uint32), 80, 1.0, 1.0, 1)
+    assert e.value.code == -6  # ETOOBIG
+    with pytest.raises(P.N2VError) as e:
+        srv.submit(np.array([og.n], dtype=np.uint32), 5, 1.0, 1.0, 1)
+    assert e.value.code == -1
+    with pytest.raises(P.N2VError) as e:
+        srv.submit(np.array([0], dtype=np.uint32), 5, 0.3, 1.0, 1)
+    assert e.value.code == -1
+    with pytest.raises(P.N2VError) as e:
+        srv.poll(12345)
+    assert e.value.code == -7
+    t = srv.submit(np.array([1, 2, 3], dtype=np.uint32), 5, 1.0, 1.0, 1)
+    wait_all(srv, [t])
+    srv.release(t)
+    with pytest.raises(P.N2VError):
+        srv.release(t)
+    srv.close()
