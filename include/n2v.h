@@ -216,14 +216,17 @@ int n2v_autotune(n2v_graph *g, uint32_t n_walks, uint32_t L, float p, float q, v
  * can be cut into rounds and admitted as memory allows).  A server keeps the
  * graph resident and runs a scheduler thread that admits submitted requests
  * into a caller-provided device pool as space frees up, cuts them into walk
- * chunks, and launches chunks of several requests together on its stream.
+ * chunks, and launches chunks of several requests together on its stream, one
+ * captured graph replay (table copy plus persistent kernel) per tick.
  * Results are identical to n2v_walk_ex with walk_base = 0 on the same
  * request, alone or in any mix.
  * ---------------------------------------------------------------------- */
 typedef struct {
     uint32_t max_queue;     /* pending requests accepted before N2V_EAGAIN (default 4096) */
     uint32_t chunk_walks;   /* walks per chunk (default 65536) */
-    uint32_t max_inflight;  /* chunks in flight per tick (default 64) */
+    uint32_t max_inflight;  /* chunks per tick (default 64, at most 256) */
+    uint32_t tick_walks;    /* walks per tick (default 2^19); ticks take chunks of the
+                               requests with the least remaining work first */
 } n2v_server_opts;
 
 typedef struct {

@@ -61,7 +61,8 @@ class ExecOpts(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("max_queue", C.c_uint32), ("chunk_walks", C.c_uint32), ("max_inflight", C.c_uint32)]
+    _fields_ = [("max_queue", C.c_uint32), ("chunk_walks", C.c_uint32), ("max_inflight", C.c_uint32),
+                ("tick_walks", C.c_uint32)]
 
 
 class Request(C.Structure):
@@ -319,7 +320,8 @@ class Done:
 class Server:
     """Continuous-batching walk server over a resident graph (see n2v.h)."""
 
-    def __init__(self, graph: Graph, pool_bytes, chunk_walks=None, max_inflight=None, max_queue=None, stream=None):
+    def __init__(self, graph: Graph, pool_bytes, chunk_walks=None, max_inflight=None, max_queue=None, stream=None,
+                 tick_walks=None):
         torch = _torch()
         self.graph = graph
         self.pool = _alloc(pool_bytes, graph.device)
@@ -331,6 +333,8 @@ class Server:
             o.max_inflight = max_inflight
         if max_queue:
             o.max_queue = max_queue
+        if tick_walks:
+            o.tick_walks = tick_walks
         self.stream = stream if stream is not None else torch.cuda.Stream(graph.device)
         h = C.c_void_p()
         check(lib().n2v_server_create(graph._h, _ptr(self.pool), self.pool.numel(), C.byref(o),

@@ -44,7 +44,7 @@ enum ReqState { QUEUED, RUNNING, DONE, FAILED };
 
 struct Req {
     uint64_t ticket;
-    uint32_t *h_starts = nullptr;  // pinned copy of the start ids
+    std::vector<uint32_t> starts;  // host copy of the start ids until admission
     uint32_t n, L, A_ret, A_out;
     uint64_t seed;
     uint64_t submit_ns = 0, start_ns = 0, done_ns = 0;
@@ -102,6 +102,7 @@ struct Pool {
 
 struct Tick {
     bool busy = false;
+    uint64_t seq = 0;            // launch order
     TableHdr *host = nullptr;    // pinned
     TableHdr *dev = nullptr;     // in the pool's reserved head
     hipGraphExec_t exec = nullptr;
@@ -110,6 +111,7 @@ struct Tick {
 };
 
 constexpr uint64_t STARVE_NS = 200ull * 1000 * 1000;
+constexpr size_t RING_BYTES = 64ull << 20;  // pinned staging for start ids
 
 }  // namespace
 
@@ -132,11 +134,44 @@ struct n2v_server {
     std::deque<uint64_t> queue;
     std::map<uint64_t, Req> reqs;
     std::vector<uint64_t> running;  // admission order
-    size_t rr = 0;                  // round-robin cursor
     uint64_t next_ticket = 1;
     bool stop = false;
     int fatal = N2V_OK;
     std::thread th;
+    // Pinned staging ring for start ids.  Space is handed out in admission
+    // order; a piece is reused once the first tick launched after its copy
+    // has retired (the copy precedes that tick on the stream).
+    char *ring = nullptr;
+    size_t ring_head = 0, ring_used = 0;
+    std::deque<std::pair<size_t, uint64_t>> ring_live;  // (bytes incl. wrap padding, tick seq)
+    uint64_t tick_seq = 0;                              // seq of the next tick to launch
+    uint64_t retired_seq = 0;                           // every tick with seq < this has retired
+
+    bool ring_alloc(size_t n, size_t *off)
+    {
+        n = (n + 255) & ~(size_t)255;
+        if (n > RING_BYTES) return false;
+        size_t at = ring_head, waste = 0;
+        if (at + n > RING_BYTES) {
+            waste = RING_BYTES - at;
+            at = 0;
+        }
+        if (ring_used + waste + n > RING_BYTES) return false;
+        ring_used += waste + n;
+        ring_live.push_back({waste + n, tick_seq});
+        ring_head = at + n;
+        *off = at;
+        return true;
+    }
+
+    void ring_retire()
+    {
+        while (!ring_live.empty() && ring_live.front().second < retired_seq) {
+            ring_used -= ring_live.front().first;
+            ring_live.pop_front();
+        }
+        if (ring_live.empty()) ring_head = ring_used = 0;
+    }
 
     int capture(Tick &t)
     {
@@ -162,10 +197,24 @@ struct n2v_server {
             Req &r = reqs[*it];
             size_t off;
             if (pool.alloc(r.bytes, &off)) {
+                size_t roff = 0;
+                const bool staged = ring_alloc((size_t)r.n * 4, &roff);
+                if (!staged && (size_t)r.n * 4 <= RING_BYTES) {  // staging full: admit later, in order
+                    pool.release(off, r.bytes);
+                    break;
+                }
                 r.off = off;
                 r.d_starts = (uint32_t *)(pool_base + off);
                 r.d_out = (uint32_t *)(pool_base + off + (((size_t)r.n * 4 + 255) & ~(size_t)255));
-                hipError_t e = hipMemcpyAsync(r.d_starts, r.h_starts, (size_t)r.n * 4, hipMemcpyHostToDevice, st);
+                hipError_t e;
+                if (staged) {
+                    memcpy(ring + roff, r.starts.data(), (size_t)r.n * 4);
+                    e = hipMemcpyAsync(r.d_starts, ring + roff, (size_t)r.n * 4, hipMemcpyHostToDevice, st);
+                } else {
+                    e = hipMemcpyAsync(r.d_starts, r.starts.data(), (size_t)r.n * 4, hipMemcpyHostToDevice, st);
+                    (void)hipStreamSynchronize(st);
+                }
+                std::vector<uint32_t>().swap(r.starts);
                 if (e != hipSuccess) {
                     r.state = FAILED;
                     r.err = hip_fail(e, "hipMemcpyAsync (starts)");
@@ -185,40 +234,45 @@ struct n2v_server {
     }
 
     // Called with mu held: fills tick t with chunks; returns the walk count.
+    // Requests with the least remaining work go first (shortest remaining
+    // processing first keeps small requests' latency low); a tick holds at
+    // most tick_walks walks so that newly admitted requests wait at most
+    // about one tick.
     uint32_t build(Tick &t)
     {
         TableHdr *h = t.host;
         t.chunks.clear();
         uint32_t nj = 0, total = 0;
         const uint32_t maxj = std::min<uint32_t>(o.max_inflight, MAX_TABLE_JOBS);
-        size_t scanned = 0;
-        while (nj < maxj && !running.empty() && scanned < running.size() * 2 + 1) {
-            if (rr >= running.size()) rr = 0;
-            Req &r = reqs[running[rr]];
-            ++scanned;
-            if (r.next >= r.n) {
-                ++rr;
-                continue;
+        std::vector<std::pair<uint32_t, uint64_t>> order;  // (remaining walks, ticket)
+        for (uint64_t tk : running) {
+            const Req &r = reqs[tk];
+            if (r.next < r.n) order.push_back({r.n - r.next, tk});
+        }
+        std::sort(order.begin(), order.end());
+        for (auto &e : order) {
+            Req &r = reqs[e.second];
+            while (r.next < r.n && nj < maxj && total < o.tick_walks) {
+                const uint32_t k = std::min(std::min(o.chunk_walks, r.n - r.next), o.tick_walks - total);
+                JobRec &jr = h->jobs[nj];
+                jr.c.out = r.d_out + (uint64_t)r.next * (r.L + 1);
+                jr.c.cnt = nullptr;
+                jr.c.checksum = nullptr;
+                jr.c.wbase = r.next;
+                jr.c.L = r.L;
+                jr.c.k0 = (uint32_t)r.seed;
+                jr.c.k1 = (uint32_t)(r.seed >> 32);
+                jr.c.A_ret = r.A_ret;
+                jr.c.A_out = r.A_out;
+                jr.starts = r.d_starts + r.next;
+                jr.n = k;
+                h->jstart[nj] = total;
+                total += k;
+                ++nj;
+                r.next += k;
+                t.chunks.push_back({r.ticket, k});
             }
-            const uint32_t k = std::min(o.chunk_walks, r.n - r.next);
-            JobRec &jr = h->jobs[nj];
-            jr.c.out = r.d_out + (uint64_t)r.next * (r.L + 1);
-            jr.c.cnt = nullptr;
-            jr.c.checksum = nullptr;
-            jr.c.wbase = r.next;
-            jr.c.L = r.L;
-            jr.c.k0 = (uint32_t)r.seed;
-            jr.c.k1 = (uint32_t)(r.seed >> 32);
-            jr.c.A_ret = r.A_ret;
-            jr.c.A_out = r.A_out;
-            jr.starts = r.d_starts + r.next;
-            jr.n = k;
-            h->jstart[nj] = total;
-            total += k;
-            ++nj;
-            r.next += k;
-            t.chunks.push_back({r.ticket, k});
-            ++rr;
+            if (nj >= maxj || total >= o.tick_walks) break;
         }
         h->njobs = nj;
         h->total = total;
@@ -231,6 +285,8 @@ struct n2v_server {
     void retire(Tick &t, int status)
     {
         const uint64_t now = now_ns();
+        if (t.seq + 1 > retired_seq) retired_seq = t.seq + 1;
+        ring_retire();
         for (auto &c : t.chunks) {
             auto it = reqs.find(c.first);
             if (it == reqs.end()) continue;
@@ -266,6 +322,7 @@ struct n2v_server {
             bool launched = false;
             if (!t.busy && fatal == N2V_OK) {
                 if (build(t) > 0) {
+                    t.seq = tick_seq++;
                     hipError_t e = hipGraphLaunch(t.exec, st);
                     if (e == hipSuccess) e = hipEventRecord(t.done, st);
                     t.busy = true;
@@ -289,6 +346,7 @@ extern "C" void n2v_server_opts_default(n2v_server_opts *o)
     o->max_queue = 4096;
     o->chunk_walks = 65536;
     o->max_inflight = 64;
+    o->tick_walks = 1u << 19;
 }
 
 extern "C" int n2v_server_create(const n2v_graph *g, void *pool, size_t pool_bytes, const n2v_server_opts *opts,
@@ -304,6 +362,7 @@ extern "C" int n2v_server_create(const n2v_graph *g, void *pool, size_t pool_byt
     if (opts) s->o = *opts;
     if (s->o.chunk_walks < 1) s->o.chunk_walks = 1;
     if (s->o.max_inflight < 1) s->o.max_inflight = 1;
+    if (s->o.tick_walks < 1) s->o.tick_walks = 1;
     n2v_exec_opts eo;
     n2v_exec_opts_default(g, &eo);
     make_exec(g, eo, &s->E);
@@ -341,6 +400,15 @@ extern "C" int n2v_server_create(const n2v_graph *g, void *pool, size_t pool_byt
             return rc;
         }
     }
+    {
+        void *h = nullptr;
+        hipError_t e = hipHostMalloc(&h, RING_BYTES, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            n2v_server_destroy(s);
+            return hip_fail(e, "hipHostMalloc (staging ring)");
+        }
+        s->ring = (char *)h;
+    }
     s->th = std::thread([s] { s->loop(); });
     *out = s;
     return N2V_OK;
@@ -361,8 +429,7 @@ extern "C" int n2v_server_destroy(n2v_server *s)
         s->th.join();
     }
     (void)hipStreamSynchronize(s->st);
-    for (auto &kv : s->reqs)
-        if (kv.second.h_starts) (void)hipHostFree(kv.second.h_starts);
+    if (s->ring) (void)hipHostFree(s->ring);
     for (Tick &t : s->ticks) {
         if (t.done) (void)hipEventSynchronize(t.done);
         if (t.exec) (void)hipGraphExecDestroy(t.exec);
@@ -387,11 +454,7 @@ extern "C" int n2v_submit(n2v_server *s, const n2v_request *r, uint64_t *ticket)
     if (((bytes + 255) & ~(size_t)255) > s->pool.size)
         return set_error(N2V_ETOOBIG, "n2v_submit: request needs %zu bytes, pool has %zu", bytes, s->pool.size);
     Req q;
-    void *h = nullptr;
-    hipError_t e = hipHostMalloc(&h, (size_t)r->n_starts * 4, hipHostMallocDefault);
-    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc (starts)");
-    memcpy(h, r->host_starts, (size_t)r->n_starts * 4);
-    q.h_starts = (uint32_t *)h;
+    q.starts.assign(r->host_starts, r->host_starts + r->n_starts);
     q.n = r->n_starts;
     q.L = r->L;
     q.A_ret = A_ret;
@@ -401,7 +464,6 @@ extern "C" int n2v_submit(n2v_server *s, const n2v_request *r, uint64_t *ticket)
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop || s->queue.size() >= s->o.max_queue) {
-            (void)hipHostFree(q.h_starts);
             if (s->stop) return set_error(N2V_EINVAL, "n2v_submit: server is stopping");
             return set_error(N2V_EAGAIN, "n2v_submit: queue full");
         }
@@ -447,7 +509,6 @@ extern "C" int n2v_release(n2v_server *s, uint64_t ticket)
         if (r.state == QUEUED || r.state == RUNNING)
             return set_error(N2V_EINVAL, "n2v_release: request %llu is not complete", (unsigned long long)ticket);
         if (r.d_starts) s->pool.release(r.off, r.bytes);
-        if (r.h_starts) (void)hipHostFree(r.h_starts);
         s->reqs.erase(it);
     }
     s->cv.notify_all();

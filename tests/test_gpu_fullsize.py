@@ -1,0 +1,78 @@
+"""Full-size workloads in the launch configuration bench.py times: every walk
+of the workload on the device, seeded samples of rows checked against the
+oracle walking its own copy of the graph, and the persistent form checked
+against the plain form on every row."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1805_00280_amd as P
+from paper_1805_00280_amd import workloads as WL
+from gpuhelp import first_mismatch, oracle_rmat, say, torch_cuda, u32
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(w, sample, attach_memo):
+    torch = torch_cuda()
+    say(f"[full] {w.name}: device graph")
+    g = P.Graph.from_rmat(*w.rmat_args(), weighted=w.weighted, device="cuda")
+    if attach_memo:
+        g.attach_memo()
+    say(f"[full] {w.name}: oracle graph")
+    og = oracle_rmat(*w.rmat_args(), w.weighted)
+    assert np.array_equal(g.off.cpu().numpy().view(np.uint64), og.off)
+    assert np.array_equal(u32(g.adj), og.adj)
+    starts = torch.arange(w.walks, dtype=torch.int64, device="cuda").remainder_(w.n).to(torch.int32)
+    out = torch.empty((w.walks, w.L + 1), dtype=torch.int32, device="cuda")
+    say(f"[full] {w.name}: persistent pass over {w.walks} walks")
+    g.walk(starts, w.L, w.p, w.q, w.seed, out=out)
+    torch.cuda.synchronize()
+    g.check_starts()
+    ids = w.sample_walk_ids(sample, seed=99)
+    got = u32(out[torch.from_numpy(ids.astype(np.int64)).cuda()])
+    say(f"[full] {w.name}: oracle on {len(ids)} sampled walks")
+    want = O.walk(og, (ids % w.n).astype(np.uint32), w.L, w.p, w.q, w.seed, wids=ids, nthreads=16)["out"]
+    assert first_mismatch(got, want) is None, first_mismatch(got, want)
+    say(f"[full] {w.name}: plain pass")
+    out2 = torch.empty_like(out)
+    g.walk(starts, w.L, w.p, w.q, w.seed, out=out2, mode=P.MODE_PLAIN)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    moves = int((out[:, 1:] != -1).sum().item())
+    say(f"[full] {w.name}: {moves} moves, persistent == plain on every row")
+    return moves
+
+
+@pytest.mark.timeout(600)
+def test_scale20_weighted_workload():
+    assert _run(WL.C2, 2048, False) > 0
+
+
+@pytest.mark.timeout(900)
+def test_scale24_skewed_workload():
+    assert _run(WL.C3, 256, True) > 0
+
+
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+def test_counts_workload_shape(mode):
+    # the scale-27 counts workload's parameters (p=2, q=1/2, r=1, L=80, chunks
+    # through walk_base) on a scale-16 graph, against the oracle's counts and checksum
+    torch = torch_cuda()
+    w = WL.C5
+    scale = 16
+    og = oracle_rmat(scale, 16, w.a, w.b, w.c, scale, False)
+    g = P.Graph.from_rmat(scale, 16, w.a, w.b, w.c, scale, device="cuda")
+    n = 1 << scale
+    ref = O.walk(og, np.arange(n, dtype=np.uint32), w.L, w.p, w.q, w.seed, want_out=False, want_counts=True,
+                 nthreads=16)
+    cnt = torch.zeros(n, dtype=torch.int32, device="cuda")
+    cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    chunk = 10000
+    for lo in range(0, n, chunk):
+        hi = min(lo + chunk, n)
+        st = torch.arange(lo, hi, dtype=torch.int32, device="cuda")
+        g.walk_counts(st, w.L, w.p, w.q, w.seed, cnt, cs, walk_base=lo, mode=mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(cnt), ref["cnt"])
+    assert int(cs.cpu().numpy().view(np.uint64)[0]) == ref["checksum"]
