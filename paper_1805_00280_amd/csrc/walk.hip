@@ -64,6 +64,7 @@ struct HubLds {
         struct {
             uint32_t xs[TX];
             uint8_t flag[TX];
+            uint32_t rc[NSUPER];  // members of N(v) per segment of N(t)
         } d;
         struct {
             uint32_t pos[SPCAP];
@@ -225,9 +226,11 @@ __device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, uin
 // Flags the tile entries equal to a block of NB x 64 entries of N(t) loaded
 // from ypos; returns how many block entries lie in the tile's value range
 // (they form a prefix of the block, N(t) being sorted).
+// With rseg > 0 each match is also counted in rc[] by the segment of N(t)
+// (rseg entries long) it lies in.
 template <int NB>
 __device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB], uint32_t ypos, uint32_t td,
-                                               uint32_t cnt, uint32_t xlast)
+                                               uint32_t cnt, uint32_t xlast, uint32_t rseg)
 {
     const int l = lane_id();
     uint32_t nin = 0;
@@ -240,7 +243,10 @@ __device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB
 #pragma unroll
             for (uint32_t step = TX / 2; step >= 1; step >>= 1)
                 if (L.a.d.xs[pos + step - 1] < y[b]) pos += step;
-            if (pos < cnt && L.a.d.xs[pos] == y[b]) L.a.d.flag[pos] = 1;
+            if (pos < cnt && L.a.d.xs[pos] == y[b]) {
+                L.a.d.flag[pos] = 1;
+                if (rseg) atomicAdd(&L.a.d.rc[(ypos + b * WAVE + l) / rseg], 1u);
+            }
         }
     }
     return nin;
@@ -252,7 +258,7 @@ __device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB
 // (most windows are short); a block consumed entirely is followed by
 // full-size blocks.  Returns the number of flagged entries.
 __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y, uint32_t td,
-                                HubLds &L, uint32_t j0, uint32_t cnt, uint32_t &ypos)
+                                HubLds &L, uint32_t j0, uint32_t cnt, uint32_t &ypos, uint32_t rseg)
 {
     const int l = lane_id();
     uint32_t xv[XPL], y0[YFIRST];
@@ -273,7 +279,7 @@ __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *
     }
     wave_lds_sync();
     const uint32_t xlast = L.a.d.xs[cnt - 1];
-    uint32_t nin = flag_block<YFIRST>(L, y0, ypos, td, cnt, xlast);
+    uint32_t nin = flag_block<YFIRST>(L, y0, ypos, td, cnt, xlast, rseg);
     ypos += nin;
     if (nin == YFIRST * WAVE) {
         while (ypos < td) {
@@ -283,7 +289,7 @@ __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *
                 const uint32_t idx = ypos + b * WAVE + l;
                 y[b] = idx < td ? Y[idx] : 0xFFFFFFFFu;
             }
-            nin = flag_block<YPL>(L, y, ypos, td, cnt, xlast);
+            nin = flag_block<YPL>(L, y, ypos, td, cnt, xlast, rseg);
             ypos += nin;
             if (nin < YPL * WAVE) break;
         }
@@ -377,6 +383,19 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         }
         S = wave_sum(pi);
     } else {
+        // The merge also yields the sketch of the reverse pair (t, index of v
+        // in N(t)) when t is a hub: common neighbours are counted per segment
+        // of N(t) as well.
+        uint16_t *rrow = nullptr;
+        uint32_t rseg = 0, rsup = 0;
+        if (row && td > E.g.d_rule) {
+            rrow = E.g.memo + (E.g.hbase[st.t] + st.jprev) * (uint64_t)MEMO_SEGS;
+            const uint32_t tsub = (td + TX - 1) / TX;
+            const uint32_t tG = (tsub + NSUPER - 1) / NSUPER;
+            rseg = tG * TX;
+            rsup = (tsub + tG - 1) / tG;
+            L.a.d.rc[l] = 0;
+        }
         uint32_t ypos = td ? wave_lower_bound(Y, td, X[0]) : 0;
         uint32_t mine = 0;
         S = 0;
@@ -387,7 +406,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             for (uint32_t sub = sp * G; sub < sub_end; ++sub) {
                 const uint32_t j0 = sub * TX;
                 const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
-                const uint32_t c = dense_flags(X, Y, td, L, j0, cnt, ypos);
+                const uint32_t c = dense_flags(X, Y, td, L, j0, cnt, ypos, rseg);
                 sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, c);
                 csp += c;
                 wave_lds_sync();
@@ -397,6 +416,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             S += sum;
         }
         if (row && (uint32_t)l < nsup) __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
+        if (rrow && (uint32_t)l < rsup) __builtin_nontemporal_store((uint16_t)(L.a.d.rc[l] + 1), rrow + l);
     }
     wave_lds_sync();
     const uint64_t r = hi64(R1, S);
@@ -421,7 +441,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     for (uint32_t sub = spx * G; sub < sub_end; ++sub) {
         const uint32_t j0 = sub * TX;
         const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
-        dense_flags(X, Y, td, L, j0, cnt, ypos);
+        dense_flags(X, Y, td, L, j0, cnt, ypos, 0);
         const uint32_t j = dense_chunk_locate(W, J, pos_t, L, j0, cnt, base, r);
         wave_lds_sync();
         if (j != SENT) return j;

@@ -223,3 +223,61 @@ def test_pair_sketches_keep_results(mode):
     got = gpu_walk(g, starts, 30, 0.25, 4.0, 8, mode=mode, memo=0)
     assert first_mismatch(got, want) is None
     g.detach_memo()
+
+
+def sketch_segments(d, tile=512, segs=64):
+    """Segment length and count of a hub row of degree d: tiles of 512 entries, grouped evenly into
+    at most 64 segments."""
+    nsub = -(-d // tile)
+    G = -(-nsub // segs)
+    return G * tile, -(-nsub // G)
+
+
+def check_sketch_rows(og, memo, d_rule, limit=6000, seed=1):
+    """Every written pair-sketch row (v, index of t in N(v)) holds, per segment of N(v), one plus the
+    number of its entries that are neighbours of t; unwritten rows are all zero."""
+    deg = og.degree()
+    hub = deg > d_rule
+    hb = np.zeros(og.n + 1, dtype=np.int64)
+    hb[1:] = np.cumsum(np.where(hub, deg, 0))
+    rows = memo
+    assert rows.shape[0] >= hb[-1]
+    touched = np.nonzero(rows[:hb[-1]].any(axis=1))[0]
+    rng = np.random.default_rng(seed)
+    pick = touched if len(touched) <= limit else rng.choice(touched, limit, replace=False)
+    hubs = np.nonzero(hub)[0]
+    owner = hubs[np.searchsorted(hb[hubs], pick, side="right") - 1]
+    for r, v in zip(pick, owner):
+        pos = int(r - hb[v])
+        nv = og.row(v)
+        t = int(nv[pos])
+        seglen, nsup = sketch_segments(int(deg[v]))
+        com = np.isin(nv, og.row(t), assume_unique=True)
+        want = np.add.reduceat(com.astype(np.int64), np.arange(0, len(nv), seglen)) + 1
+        got = rows[r]
+        assert np.array_equal(got[:nsup], want), (int(v), t, got[:nsup], want)
+        assert not got[nsup:].any(), (int(v), t)
+    return len(touched)
+
+
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+def test_pair_sketch_contents(mode):
+    # the sketches written during a call (by forward merges and by the reverse pairs they also
+    # count) hold exact per-segment common-neighbour counts
+    import torch
+    torch_cuda()
+    og = oracle_rmat(14, 16, *SKEW, 14, False)
+    g = gpu_graph_from_oracle(og, d_rule=40)
+    g.attach_memo()
+    deg = og.degree()
+    hubs = np.argsort(deg)[-256:].astype(np.uint32)
+    starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
+    got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=100000)
+    torch.cuda.synchronize()
+    memo = g.memo.cpu().numpy().view(np.uint16).reshape(-1, 64)
+    n = check_sketch_rows(og, memo, 40)
+    say(f"[walk] sketches mode={mode}: {n} rows written")
+    assert n > 1000
+    want = oracle_walk(og, starts, 20, 0.25, 4.0, 8, d_rule=40)
+    assert first_mismatch(got, want) is None
+    g.detach_memo()
