@@ -54,7 +54,7 @@ class GraphOpts(C.Structure):
 class ExecOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("t_wave", C.c_uint32), ("t_sparse", C.c_uint32),
                 ("sparse_ratio", C.c_uint32), ("waves_per_cu", C.c_uint32), ("block", C.c_uint32),
-                ("memo", C.c_uint32)]
+                ("memo", C.c_uint32), ("t_wg", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +75,7 @@ class Result(C.Structure):
                 ("start_ns", C.c_uint64), ("done_ns", C.c_uint64)]
 
 
+ABI_VERSION = 2  # layout of the option structs below
 _lib = None
 
 
@@ -120,6 +121,9 @@ def lib():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = res
+    if L.n2v_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH}: ABI version {L.n2v_abi_version()}, this binding expects {ABI_VERSION}; "
+                           "rebuild the library")
     _lib = L
     return L
 

@@ -16,8 +16,10 @@ constexpr uint32_t SENT = 0xFFFFFFFFu;
 constexpr int WAVE = 64;
 // Segments per pair sketch: a sketch of the move (t -> v) at a hub v holds,
 // for each of up to MEMO_SEGS segments of N(v), one plus the number of
-// members of N(t) in that segment (0 = not known yet).
+// members of N(t) in that segment (0 = not known yet), then, per segment, a
+// start hint into N(t) (MEMO_ROW u16 per sketch).
 constexpr int MEMO_SEGS = 64;
+constexpr int MEMO_ROW = 2 * MEMO_SEGS;
 // Walk counters a graph hands out round-robin to persistent launches: up to
 // this many launches on one graph may overlap.
 constexpr int CURSOR_SLOTS = 64;
@@ -49,7 +51,7 @@ struct DevGraph {
     const uint16_t *wt;    // m, or null for an unweighted graph
     const uint64_t *wsum;  // n: row weight sums (weighted graphs only)
     const uint64_t *hbase; // n+1: first memo entry of each row of degree > d_rule
-    uint16_t *memo;        // pair sketches (hbase[n] entries of MEMO_SEGS u16) or null
+    uint16_t *memo;        // pair sketches (hbase[n] rows of MEMO_ROW u16) or null
     uint32_t *status;      // device flags: bit 0 = a start id was out of range
     uint32_t *cursors;     // CURSOR_SLOTS walk counters, one per concurrent call
     uint32_t n;

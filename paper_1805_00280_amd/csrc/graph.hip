@@ -243,7 +243,7 @@ extern "C" int n2v_graph_info(const n2v_graph *g, uint32_t *n, uint64_t *m, uint
 extern "C" int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes)
 {
     if (!g || !bytes) return set_error(N2V_EINVAL, "n2v_graph_memo_bytes: null argument");
-    *bytes = g->weighted ? 0 : (size_t)g->hub_entries * MEMO_SEGS * sizeof(uint16_t);
+    *bytes = g->weighted ? 0 : (size_t)g->hub_entries * MEMO_ROW * sizeof(uint16_t);
     return N2V_OK;
 }
 

@@ -64,7 +64,8 @@ struct HubLds {
         struct {
             uint32_t xs[TX];
             uint8_t flag[TX];
-            uint32_t rc[NSUPER];  // members of N(v) per segment of N(t)
+            uint32_t rc[NSUPER];  // reverse sketch: members of N(v) per segment of N(t)
+            uint32_t rh[NSUPER];  // reverse sketch: encoded start hints
         } d;
         struct {
             uint32_t pos[SPCAP];
@@ -226,26 +227,52 @@ __device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, uin
 // Flags the tile entries equal to a block of NB x 64 entries of N(t) loaded
 // from ypos; returns how many block entries lie in the tile's value range
 // (they form a prefix of the block, N(t) being sorted).
-// With rseg > 0 each match is also counted in rc[] by the segment of N(t)
-// (rseg entries long) it lies in.
+// Sketch rows: MEMO_SEGS counts (one plus the number of members of N(t) in
+// a segment of N(v); 0 = unknown), then MEMO_SEGS start hints: hint h > 0 of a
+// segment says that its merge may start streaming N(t) at index
+// (h - 1) << hint_shift(deg t), which is at or below the lower bound in N(t)
+// of the segment's first entry (so the skipped entries cannot match).
+__device__ __forceinline__ uint32_t hint_shift(uint32_t d)
+{
+    const uint32_t b = 32 - __clz(d);
+    return b > 15 ? b - 15 : 0;
+}
+
+// The sketch of the reverse pair (t, index of v in N(t)) that a merge of N(v)
+// with N(t) also yields: counts of common entries per segment of N(t) and,
+// for each segment's first entry, its lower bound in N(v) as a start hint.
+struct RevSketch {
+    uint32_t rseg;   // segment length of N(t); 0: not collected
+    uint32_t shift;  // hint_shift(deg v)
+    uint32_t *rc;    // LDS counts
+    uint32_t *rh;    // LDS encoded hints
+};
+
+// Flags the tile entries equal to a block of NB x 64 entries of N(t) loaded
+// from ypos; returns how many block entries lie in the tile's value range
+// (they form a prefix of the block, N(t) being sorted).
 template <int NB>
 __device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB], uint32_t ypos, uint32_t td,
-                                               uint32_t cnt, uint32_t xlast, uint32_t rseg)
+                                               uint32_t j0, uint32_t cnt, uint32_t xlast, const RevSketch &R)
 {
     const int l = lane_id();
     uint32_t nin = 0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const bool in = ypos + b * WAVE + l < td && y[b] <= xlast;
+        const uint32_t idx = ypos + b * WAVE + l;
+        const bool in = idx < td && y[b] <= xlast;
         nin += __popcll(ballot(in));
         if (in) {  // branchless search over the padded tile: pos = entries below y
             uint32_t pos = 0;
 #pragma unroll
             for (uint32_t step = TX / 2; step >= 1; step >>= 1)
                 if (L.a.d.xs[pos + step - 1] < y[b]) pos += step;
-            if (pos < cnt && L.a.d.xs[pos] == y[b]) {
-                L.a.d.flag[pos] = 1;
-                if (rseg) atomicAdd(&L.a.d.rc[(ypos + b * WAVE + l) / rseg], 1u);
+            const bool hit = pos < cnt && L.a.d.xs[pos] == y[b];
+            if (hit) L.a.d.flag[pos] = 1;
+            if (R.rseg && (hit || (idx & (TX - 1)) == 0)) {
+                const uint32_t k = idx / R.rseg;
+                if (hit) atomicAdd(&R.rc[k], 1u);
+                if (idx == k * R.rseg) R.rh[k] = ((j0 + pos) >> R.shift) + 1;
             }
         }
     }
@@ -258,7 +285,7 @@ __device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB
 // (most windows are short); a block consumed entirely is followed by
 // full-size blocks.  Returns the number of flagged entries.
 __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y, uint32_t td,
-                                HubLds &L, uint32_t j0, uint32_t cnt, uint32_t &ypos, uint32_t rseg)
+                                HubLds &L, uint32_t j0, uint32_t cnt, uint32_t &ypos, const RevSketch &R)
 {
     const int l = lane_id();
     uint32_t xv[XPL], y0[YFIRST];
@@ -279,7 +306,7 @@ __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *
     }
     wave_lds_sync();
     const uint32_t xlast = L.a.d.xs[cnt - 1];
-    uint32_t nin = flag_block<YFIRST>(L, y0, ypos, td, cnt, xlast, rseg);
+    uint32_t nin = flag_block<YFIRST>(L, y0, ypos, td, j0, cnt, xlast, R);
     ypos += nin;
     if (nin == YFIRST * WAVE) {
         while (ypos < td) {
@@ -289,7 +316,7 @@ __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *
                 const uint32_t idx = ypos + b * WAVE + l;
                 y[b] = idx < td ? Y[idx] : 0xFFFFFFFFu;
             }
-            nin = flag_block<YPL>(L, y, ypos, td, cnt, xlast, rseg);
+            nin = flag_block<YPL>(L, y, ypos, td, j0, cnt, xlast, R);
             ypos += nin;
             if (nin < YPL * WAVE) break;
         }
@@ -349,10 +376,30 @@ __device__ __forceinline__ uint64_t seg_pi(const JobCtx &J, uint32_t pos_t, uint
     return s;
 }
 
+// Sketch row of the move at v from t (t at index pos_t of N(v)), or null.
+__device__ __forceinline__ uint16_t *sketch_row(const Exec &E, uint32_t v, uint32_t pos_t)
+{
+    return E.g.memo + (E.g.hbase[v] + pos_t) * (uint64_t)MEMO_ROW;
+}
+
+// Reverse sketch to collect while merging a cold move at v (a hub) from t.
+__device__ __forceinline__ uint16_t *rev_setup(const Exec &E, const WS &st, uint32_t *rc, uint32_t *rh, RevSketch &R)
+{
+    R.rseg = 0;
+    R.shift = hint_shift(st.vd);
+    R.rc = rc;
+    R.rh = rh;
+    if (st.td <= E.g.d_rule) return nullptr;
+    const uint32_t tsub = (st.td + TX - 1) / TX;
+    const uint32_t tG = (tsub + NSUPER - 1) / NSUPER;
+    R.rseg = tG * TX;
+    return sketch_row(E, st.t, st.jprev);
+}
+
 // Dense inverse CDF of a second-order move over all of N(v): per-segment sums
 // (from the pair sketch when it is known, else by a merge-intersection pass
-// that also fills the sketch), then one segment is recomputed to find the
-// entry whose prefix sum first exceeds r.
+// that also fills the sketch and its reverse), then one segment is recomputed
+// to find the entry whose prefix sum first exceeds r.
 __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, uint64_t R1)
 {
     const int l = lane_id();
@@ -364,13 +411,17 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     const uint32_t G = (nsub + NSUPER - 1) / NSUPER;  // tiles per segment
     const uint32_t nsup = (nsub + G - 1) / G;
     const uint32_t seglen = G * TX;
+    const uint32_t hs = hint_shift(td);
     uint16_t *row = nullptr;
-    if (E.g.memo && !W && pos_t != SENT && dv > E.g.d_rule)
-        row = E.g.memo + (E.g.hbase[st.v] + pos_t) * (uint64_t)MEMO_SEGS;
+    if (E.g.memo && !W && pos_t != SENT && dv > E.g.d_rule) row = sketch_row(E, st.v, pos_t);
     bool warm = false;
-    uint32_t known = 1;
+    uint32_t known = 1, ystart = SENT;  // per segment (lane): count + 1, start of N(t) or SENT
     if (row) {
-        if ((uint32_t)l < nsup) known = row[l];
+        if ((uint32_t)l < nsup) {
+            known = row[l];
+            const uint32_t h = row[MEMO_SEGS + l];
+            if (h) ystart = (h - 1) << hs;
+        }
         warm = ballot(known == 0) == 0;
     }
     uint64_t S;
@@ -383,18 +434,13 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         }
         S = wave_sum(pi);
     } else {
-        // The merge also yields the sketch of the reverse pair (t, index of v
-        // in N(t)) when t is a hub: common neighbours are counted per segment
-        // of N(t) as well.
+        RevSketch R;
         uint16_t *rrow = nullptr;
-        uint32_t rseg = 0, rsup = 0;
-        if (row && td > E.g.d_rule) {
-            rrow = E.g.memo + (E.g.hbase[st.t] + st.jprev) * (uint64_t)MEMO_SEGS;
-            const uint32_t tsub = (td + TX - 1) / TX;
-            const uint32_t tG = (tsub + NSUPER - 1) / NSUPER;
-            rseg = tG * TX;
-            rsup = (tsub + tG - 1) / tG;
+        if (row) rrow = rev_setup(E, st, L.a.d.rc, L.a.d.rh, R);
+        else R.rseg = 0;
+        if (R.rseg) {
             L.a.d.rc[l] = 0;
+            L.a.d.rh[l] = 0;
         }
         uint32_t ypos = td ? wave_lower_bound(Y, td, X[0]) : 0;
         uint32_t mine = 0;
@@ -402,11 +448,12 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         for (uint32_t sp = 0; sp < nsup; ++sp) {
             uint64_t sum = 0;
             uint32_t csp = 0;
+            if ((uint32_t)l == sp) ystart = ypos;
             const uint32_t sub_end = nsub < (sp + 1) * G ? nsub : (sp + 1) * G;
             for (uint32_t sub = sp * G; sub < sub_end; ++sub) {
                 const uint32_t j0 = sub * TX;
                 const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
-                const uint32_t c = dense_flags(X, Y, td, L, j0, cnt, ypos, rseg);
+                const uint32_t c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
                 sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, c);
                 csp += c;
                 wave_lds_sync();
@@ -415,8 +462,15 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             if ((uint32_t)l == sp) mine = csp;
             S += sum;
         }
-        if (row && (uint32_t)l < nsup) __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
-        if (rrow && (uint32_t)l < rsup) __builtin_nontemporal_store((uint16_t)(L.a.d.rc[l] + 1), rrow + l);
+        if (row && (uint32_t)l < nsup) {
+            __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
+            __builtin_nontemporal_store((uint16_t)((ystart >> hs) + 1), row + MEMO_SEGS + l);
+        }
+        const uint32_t rsup = R.rseg ? (td + R.rseg - 1) / R.rseg : 0;
+        if (rrow && (uint32_t)l < rsup) {
+            __builtin_nontemporal_store((uint16_t)(L.a.d.rc[l] + 1), rrow + l);
+            __builtin_nontemporal_store((uint16_t)L.a.d.rh[l], rrow + MEMO_SEGS + l);
+        }
     }
     wave_lds_sync();
     const uint64_t r = hi64(R1, S);
@@ -436,12 +490,15 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     }
     wave_lds_sync();
     const uint32_t x0 = spx * seglen;
-    uint32_t ypos = td ? wave_lower_bound(Y, td, X[x0]) : 0;
+    uint32_t ypos = lane_val(ystart, (int)spx);
+    if (ypos == SENT) ypos = td ? wave_lower_bound(Y, td, X[x0]) : 0;
+    if (ypos > td) ypos = td;
+    const RevSketch none = {0, 0, nullptr, nullptr};
     const uint32_t sub_end = nsub < (spx + 1) * G ? nsub : (spx + 1) * G;
     for (uint32_t sub = spx * G; sub < sub_end; ++sub) {
         const uint32_t j0 = sub * TX;
         const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
-        dense_flags(X, Y, td, L, j0, cnt, ypos, 0);
+        dense_flags(X, Y, td, L, j0, cnt, ypos, none);
         const uint32_t j = dense_chunk_locate(W, J, pos_t, L, j0, cnt, base, r);
         wave_lds_sync();
         if (j != SENT) return j;
@@ -600,8 +657,148 @@ __device__ __forceinline__ bool use_sparse(const Exec &E, const WS &st)
     return (uint64_t)st.td * E.sparse_ratio * lg < (uint64_t)st.vd + st.td;
 }
 
+// ------------------------------------------------ workgroup per hub move
+constexpr int HBLOCK = 256;  // plain hub kernel workgroup
+constexpr int HWAVES = HBLOCK / WAVE;
+
+// LDS a workgroup shares while it evaluates one move together.
+struct BlkLds {
+    uint64_t csum[NSUPER];   // per-segment sums of pi
+    uint32_t ystart[NSUPER]; // per-segment start in N(t) (SENT: search)
+    uint32_t rc[NSUPER];     // reverse sketch counts
+    uint32_t rh[NSUPER];     // reverse sketch hints
+    uint64_t part[HWAVES];   // tile sums of one locate round
+    uint32_t q;              // dequeued item
+    uint32_t warm;
+    uint32_t ans;
+};
+
+// Dense inverse CDF of one move by a whole workgroup (state uniform across
+// the group): the same arithmetic as hub_dense, with the segments of N(v)
+// split among the wavefronts (each merging its share against N(t) from its
+// own lower bound) and the tiles of the located segment taken HWAVES at a
+// time.  Every wavefront of the group must call it; it synchronises the group.
+__device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, BlkLds &B, uint64_t R1)
+{
+    const int l = lane_id();
+    const uint32_t wv = threadIdx.x / WAVE;
+    const uint32_t *__restrict__ X = E.g.adj + st.vo;
+    const uint32_t *__restrict__ Y = E.g.adj + st.to;
+    const uint16_t *__restrict__ W = E.g.wt ? E.g.wt + st.vo : nullptr;
+    const uint32_t dv = st.vd, td = st.td, pos_t = st.pos_t;
+    const uint32_t nsub = (dv + TX - 1) / TX;
+    const uint32_t G = (nsub + NSUPER - 1) / NSUPER;
+    const uint32_t nsup = (nsub + G - 1) / G;
+    const uint32_t seglen = G * TX;
+    const uint32_t hs = hint_shift(td);
+    uint16_t *row = nullptr;
+    if (E.g.memo && !W && pos_t != SENT && dv > E.g.d_rule) row = sketch_row(E, st.v, pos_t);
+    // one wavefront reads the sketch, so that the whole group takes one branch
+    // even while another group is filling the same row
+    if (wv == 0) {
+        bool warm = false;
+        uint32_t known = 1, ys = SENT;
+        if (row) {
+            if ((uint32_t)l < nsup) {
+                known = row[l];
+                const uint32_t h = row[MEMO_SEGS + l];
+                if (h) ys = (h - 1) << hs;
+            }
+            warm = ballot(known == 0) == 0;
+        }
+        if (warm && (uint32_t)l < nsup) {
+            const uint32_t a = l * seglen;
+            B.csum[l] = seg_pi(J, pos_t, a, dv - a < seglen ? dv - a : seglen, known - 1);
+        }
+        B.ystart[l] = ys;
+        B.rc[l] = 0;
+        B.rh[l] = 0;
+        if (l == 0) B.warm = warm;
+    }
+    __syncthreads();
+    if (!B.warm) {
+        RevSketch R;
+        uint16_t *rrow = nullptr;
+        if (row) rrow = rev_setup(E, st, B.rc, B.rh, R);
+        else R.rseg = 0;
+        const uint32_t sp0 = wv * nsup / HWAVES, sp1 = (wv + 1) * nsup / HWAVES;
+        if (sp0 < sp1) {
+            uint32_t ypos = td ? wave_lower_bound(Y, td, X[sp0 * seglen]) : 0;
+            for (uint32_t sp = sp0; sp < sp1; ++sp) {
+                uint64_t sum = 0;
+                uint32_t csp = 0;
+                const uint32_t ys = ypos;
+                const uint32_t sub_end = nsub < (sp + 1) * G ? nsub : (sp + 1) * G;
+                for (uint32_t sub = sp * G; sub < sub_end; ++sub) {
+                    const uint32_t j0 = sub * TX;
+                    const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
+                    const uint32_t c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
+                    sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, c);
+                    csp += c;
+                    wave_lds_sync();
+                }
+                if (l == 0) {
+                    B.csum[sp] = sum;
+                    B.ystart[sp] = ys;
+                    if (row) {
+                        __builtin_nontemporal_store((uint16_t)(csp + 1), row + sp);
+                        __builtin_nontemporal_store((uint16_t)((ys >> hs) + 1), row + MEMO_SEGS + sp);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t rsup = R.rseg ? (td + R.rseg - 1) / R.rseg : 0;
+        if (wv == 0 && rrow && (uint32_t)l < rsup) {
+            __builtin_nontemporal_store((uint16_t)(B.rc[l] + 1), rrow + l);
+            __builtin_nontemporal_store((uint16_t)B.rh[l], rrow + MEMO_SEGS + l);
+        }
+    }
+    // every wavefront finds the same segment from the shared sums
+    const uint64_t c = (uint32_t)l < nsup ? B.csum[l] : 0;
+    const uint64_t inc = wave_incl_scan(c);
+    const uint64_t S = lane_val64(inc, WAVE - 1);
+    const uint64_t r = hi64(R1, S);
+    const uint64_t m = ballot((uint32_t)l < nsup && inc > r);
+    const uint32_t spx = m ? (uint32_t)first_lane(m) : nsup - 1;
+    uint64_t base = lane_val64(inc - c, (int)spx);
+    const uint32_t yseg = B.ystart[spx];
+    const RevSketch none = {0, 0, nullptr, nullptr};
+    const uint32_t sub_end = nsub < (spx + 1) * G ? nsub : (spx + 1) * G;
+    for (uint32_t b = spx * G; b < sub_end; b += HWAVES) {
+        const uint32_t sub = b + wv;
+        const bool has = sub < sub_end;
+        const uint32_t j0 = sub * TX;
+        const uint32_t cnt = has ? (dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX) : 0;
+        uint64_t tsum = 0;
+        if (has) {
+            uint32_t ypos = sub == spx * G ? yseg : SENT;
+            if (ypos == SENT) ypos = td ? wave_lower_bound(Y, td, X[j0]) : 0;
+            if (ypos > td) ypos = td;
+            const uint32_t cc = dense_flags(X, Y, td, L, j0, cnt, ypos, none);
+            tsum = W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, cc);
+        }
+        if (l == 0) B.part[wv] = tsum;
+        __syncthreads();
+        uint64_t before = base, after = base;
+        for (int k = 0; k < HWAVES; ++k) {
+            if ((uint32_t)k < wv) before += B.part[k];
+            after += B.part[k];
+        }
+        if (has && before <= r && before + tsum > r) {
+            const uint32_t j = dense_chunk_locate(W, J, pos_t, L, j0, cnt, before, r);
+            if (l == 0) B.ans = j;
+        }
+        wave_lds_sync();
+        __syncthreads();
+        if (after > r) return B.ans;
+        base = after;
+    }
+    return dv - 1;  // not reached: the last prefix equals S > r
+}
+
 // Inverse CDF of one move by a wavefront (state uniform across lanes).
-__device__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &st_in, uint32_t kidx, HubLds &L)
+__device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &st_in, uint32_t kidx, HubLds &L)
 {
     const WS st = uniform_ws(st_in);
     const R4 rr = philox(J.k0, J.k1, J.wbase + st.i, st.s, kidx, 0u);
@@ -943,20 +1140,27 @@ __device__ __forceinline__ void plain_finish(const Exec &E, const JobCtx &J, WS 
     if (!wave || lane_id() == 0) state[st.i] = make_uint4(end ? SENT : x, st.v, rev, j);
 }
 
+// Hub moves are queued for k_plain_hub: dense moves at degree > t_wg at the
+// top of hubq (growing down, one workgroup each), all others at the bottom.
 template <bool WALKS, bool COUNTS>
 __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
-                                                    uint32_t *__restrict__ hubq, uint32_t *__restrict__ hubn)
+                                                    uint32_t *__restrict__ hubq, uint32_t *__restrict__ hubn,
+                                                    uint32_t *__restrict__ bign)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t csum = 0;
-    bool push = false;
+    bool push = false, big = false;
     uint32_t item = 0;
     if (i < S.n) {
         WS st;
         if (plain_load(E, state[i], i, s, st)) {
             if (st.vd > E.g.d_rule) {
-                push = true;
                 item = i;
+                // workgroups pay off on full merges: with sketches, only moves
+                // whose sketch looks unknown (first count still 0) go to them
+                big = s > 0 && st.vd > E.t_wg && !use_sparse(E, st) &&
+                      !(E.g.memo && !E.g.wt && st.pos_t != SENT && sketch_row(E, st.v, st.pos_t)[0] != 0);
+                push = !big;
             } else {
                 uint32_t j;
                 if (thread_reject(E, S.c, st, j)) plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, false);
@@ -975,22 +1179,56 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
         base = shfl32(base, lead);
         if (push) hubq[base + __popcll(m & lanemask_lt())] = item;
     }
+    const uint64_t mb = ballot(big);
+    if (mb) {
+        uint32_t base = 0;
+        const int lead = first_lane(mb);
+        if (lane_id() == lead) base = atomicAdd(bign, (uint32_t)__popcll(mb));
+        base = shfl32(base, lead);
+        if (big) hubq[S.n - 1 - (base + __popcll(mb & lanemask_lt()))] = item;
+    }
     if (COUNTS) {
         csum = wave_sum(csum);
         if (lane_id() == 0 && csum) atomicAdd(S.c.checksum, (unsigned long long)csum);
     }
 }
 
-// One workgroup-resident wavefront per hub move of this superstep.
+// The hub moves of this superstep: first the large dense ones, one workgroup
+// each (largest work first shortens the superstep's tail), then the rest,
+// one wavefront each.
 template <bool WALKS, bool COUNTS>
-__global__ __launch_bounds__(256, 6) void k_plain_hub(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
-                                                      const uint32_t *__restrict__ hubq, const uint32_t *__restrict__ hubn,
-                                                      uint32_t *__restrict__ hubd)
+__global__ __launch_bounds__(HBLOCK, 5) void k_plain_hub(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
+                                                         const uint32_t *__restrict__ hubq,
+                                                         const uint32_t *__restrict__ hubn, uint32_t *__restrict__ hubd,
+                                                         const uint32_t *__restrict__ bign, uint32_t *__restrict__ bigd)
 {
-    __shared__ HubLds lds[256 / WAVE];
+    __shared__ HubLds lds[HBLOCK / WAVE];
+    __shared__ BlkLds blk;
     HubLds &L = lds[threadIdx.x / WAVE];
-    const uint32_t n = *hubn;
+    const bool lead = threadIdx.x < WAVE;
     uint64_t csum = 0;
+    const uint32_t nb = *bign;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) blk.q = atomicAdd(bigd, 1u);
+        __syncthreads();
+        const uint32_t q = blk.q;
+        if (q >= nb) break;
+        const uint32_t i = uni(hubq[S.n - 1 - q]);
+        WS st;
+        plain_load(E, state[i], i, s, st);
+        st = uniform_ws(st);
+        const R4 rr = philox(S.c.k0, S.c.k1, S.c.wbase + st.i, st.s, 0u, 0u);
+        uint32_t j = block_dense(E, S.c, st, L, blk, join64(rr.x, rr.y));
+        if (lead) {
+            if (j >= st.vd) {
+                if (lane_id() == 0) atomicOr(E.g.status, 2u);
+                j = st.vd - 1;
+            }
+            plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, true);
+        }
+    }
+    const uint32_t n = *hubn;
     for (;;) {
         uint32_t q = 0;
         if (lane_id() == 0) q = atomicAdd(hubd, 1u);
@@ -1048,7 +1286,7 @@ size_t plain_ws(uint32_t n_starts, uint32_t L)
     Carver c(nullptr, 0);
     c.take<uint4>(n_starts ? n_starts : 1);
     c.take<uint32_t>(n_starts ? n_starts : 1);
-    c.take<uint32_t>(2 * ((uint64_t)L + 1));
+    c.take<uint32_t>(4 * ((uint64_t)L + 1));
     return c.total();
 }
 
@@ -1080,18 +1318,22 @@ int launch_plain(const Exec &E, const OneJob &S, void *ws, int dev, hipStream_t 
     Carver c(ws, (size_t)-1);
     uint4 *state = c.take<uint4>(S.n ? S.n : 1);
     uint32_t *hubq = c.take<uint32_t>(S.n ? S.n : 1);
-    uint32_t *hubn = c.take<uint32_t>(2 * ((uint64_t)S.c.L + 1));  // per superstep: enqueued, dequeued
+    // per superstep: enqueued and dequeued wavefront moves, then workgroup moves
+    uint32_t *hubn = c.take<uint32_t>(4 * ((uint64_t)S.c.L + 1));
     uint32_t *hubd = hubn + S.c.L + 1;
+    uint32_t *bign = hubd + S.c.L + 1;
+    uint32_t *bigd = bign + S.c.L + 1;
     const uint32_t blocks = (S.n + 255) / 256;
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, hubn, 2 * (S.c.L + 1));
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, hubn, 4 * (S.c.L + 1));
     hipLaunchKernelGGL((k_plain_init<W, C>), dim3(blocks), dim3(256), 0, st, E, S, state);
     N2V_HIP(hipGetLastError());
     DevInfo &d = dev_info(dev);
     const uint32_t hub_blocks = (uint32_t)d.cus * 8;
     for (uint32_t s = 0; s < S.c.L; ++s) {
-        hipLaunchKernelGGL((k_plain_step<W, C>), dim3(blocks), dim3(256), 0, st, E, S, s, state, hubq, hubn + s);
-        hipLaunchKernelGGL((k_plain_hub<W, C>), dim3(hub_blocks), dim3(256), 0, st, E, S, s, state, hubq,
-                           (const uint32_t *)(hubn + s), hubd + s);
+        hipLaunchKernelGGL((k_plain_step<W, C>), dim3(blocks), dim3(256), 0, st, E, S, s, state, hubq, hubn + s,
+                           bign + s);
+        hipLaunchKernelGGL((k_plain_hub<W, C>), dim3(hub_blocks), dim3(HBLOCK), 0, st, E, S, s, state, hubq,
+                           (const uint32_t *)(hubn + s), hubd + s, (const uint32_t *)(bign + s), bigd + s);
     }
     N2V_HIP(hipGetLastError());
     return N2V_OK;
@@ -1123,6 +1365,7 @@ void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E)
     if (!o.memo) E->g.memo = nullptr;
     E->t_wave = o.t_wave;
     E->t_sparse = o.t_sparse;
+    E->t_wg = o.t_wg < g->dg.d_rule ? g->dg.d_rule : o.t_wg;
     E->sparse_ratio = o.sparse_ratio < 1 ? 1 : o.sparse_ratio;
 }
 
@@ -1170,6 +1413,7 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
     o->waves_per_cu = 0;
     o->block = 256;
     o->memo = 1;
+    o->t_wg = 8192;
 }
 
 extern "C" int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_t L, const n2v_exec_opts *opts,

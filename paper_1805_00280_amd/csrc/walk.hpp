@@ -13,6 +13,7 @@ struct Exec {
     uint32_t t_wave;        // rejection moves at degree > t_wave run wave-cooperatively
     uint32_t t_sparse;      // largest deg(t) for the sparse hub path
     uint32_t sparse_ratio;  // cost weight of one search against streaming
+    uint32_t t_wg;          // plain form: dense hub moves at degree > t_wg use a whole workgroup
     uint32_t *cursor;       // next unassigned walk of a single-job launch (zeroed before it)
 };
 

@@ -37,6 +37,8 @@ def test_scale12_workload_full_parity(c1, mode):
 @pytest.mark.parametrize("opts", [
     dict(t_wave=0), dict(t_wave=16), dict(t_wave=1024), dict(sparse_ratio=1), dict(sparse_ratio=100000),
     dict(t_sparse=0), dict(waves_per_cu=4), dict(t_wave=0, sparse_ratio=1, waves_per_cu=1),
+    dict(mode=P.MODE_PLAIN, t_wg=0), dict(mode=P.MODE_PLAIN, t_wg=0, sparse_ratio=100000),
+    dict(mode=P.MODE_PLAIN, t_wg=1 << 31),
 ])
 def test_execution_options_do_not_change_results(opts):
     torch_cuda()
@@ -114,6 +116,36 @@ def test_big_hubs_dense_and_sparse_paths():
         say(f"[walk] big hubs ratio={ratio}")
         got = gpu_walk(g, starts, 12, 0.5, 2.0, 3, sparse_ratio=ratio)
         assert first_mismatch(got, want) is None, first_mismatch(got, want)
+        # plain form, every dense hub move evaluated by a whole workgroup
+        say(f"[walk] big hubs ratio={ratio} workgroup class")
+        got = gpu_walk(g, starts, 12, 0.5, 2.0, 3, sparse_ratio=ratio, mode=P.MODE_PLAIN, t_wg=0)
+        assert first_mismatch(got, want) is None, first_mismatch(got, want)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("memo", [0, 1])
+def test_workgroup_hub_class(weighted, memo):
+    # the plain form hands dense hub moves above t_wg to whole workgroups: the segments of N(v)
+    # are split among its wavefronts, and the located segment's tiles are taken four at a time
+    torch = torch_cuda()
+    og = oracle_rmat(13, 16, *SKEW, 13, weighted)
+    g = gpu_graph_from_oracle(og, d_rule=100)
+    if memo and not weighted:
+        g.attach_memo()
+    deg = og.degree()
+    hubs = np.argsort(deg)[-128:].astype(np.uint32)
+    starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
+    pq = (1.0, 0.5) if weighted else (0.25, 4.0)
+    want = oracle_walk(og, starts, 25, *pq, 31, d_rule=100)
+    for t_wg in (0, 400, 1 << 31):
+        say(f"[walk] workgroup class weighted={weighted} memo={memo} t_wg={t_wg}")
+        got = gpu_walk(g, starts, 25, *pq, 31, mode=P.MODE_PLAIN, t_wg=t_wg, sparse_ratio=100000, memo=memo)
+        assert first_mismatch(got, want) is None, (t_wg, first_mismatch(got, want))
+    if memo and not weighted:
+        torch.cuda.synchronize()
+        n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128), 100)
+        assert n > 100
+        g.detach_memo()
 
 
 def test_walk_base_selects_stream(c1):
@@ -167,8 +199,9 @@ def test_directed_dead_end_and_tiny_graphs():
             assert first_mismatch(got, want) is None, (n, d_rule, first_mismatch(got, want))
 
 
-@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN, "plain_wg"])
 def test_counts_and_checksum(mode):
+    kw = dict(mode=P.MODE_PLAIN, t_wg=0) if mode == "plain_wg" else dict(mode=mode)
     torch = torch_cuda()
     og = oracle_rmat(12, 16, *DEF, 5, False)
     g = gpu_graph_from_oracle(og, d_rule=64)
@@ -179,7 +212,7 @@ def test_counts_and_checksum(mode):
     # three chunks with walk_base, counts accumulate
     for lo in range(0, len(starts), 5000):
         hi = min(lo + 5000, len(starts))
-        g.walk_counts(starts_tensor(torch, starts[lo:hi]), 20, 2.0, 0.5, 5, cnt, cs, walk_base=lo, mode=mode)
+        g.walk_counts(starts_tensor(torch, starts[lo:hi]), 20, 2.0, 0.5, 5, cnt, cs, walk_base=lo, **kw)
     torch.cuda.synchronize()
     assert np.array_equal(u32(cnt), ref["cnt"])
     assert int(cs.cpu().numpy().view(np.uint64)[0]) == ref["checksum"]
@@ -187,7 +220,7 @@ def test_counts_and_checksum(mode):
     out = torch.empty((len(starts), 21), dtype=torch.int32, device="cuda")
     cnt.zero_()
     cs.zero_()
-    g.walk_counts(starts_tensor(torch, starts), 20, 2.0, 0.5, 5, cnt, cs, out=out, mode=mode)
+    g.walk_counts(starts_tensor(torch, starts), 20, 2.0, 0.5, 5, cnt, cs, out=out, **kw)
     torch.cuda.synchronize()
     assert np.array_equal(u32(out), ref["out"])
     assert np.array_equal(u32(cnt), ref["cnt"])
@@ -233,35 +266,53 @@ def sketch_segments(d, tile=512, segs=64):
     return G * tile, -(-nsub // G)
 
 
+def hint_shift(d):
+    return max(0, int(d).bit_length() - 15)
+
+
 def check_sketch_rows(og, memo, d_rule, limit=6000, seed=1):
     """Every written pair-sketch row (v, index of t in N(v)) holds, per segment of N(v), one plus the
-    number of its entries that are neighbours of t; unwritten rows are all zero."""
+    number of its entries that are neighbours of t, and start hints into N(t) at or below the lower
+    bound of the segment's first entry and not below the end of the previous segment's matches;
+    unwritten rows and entries are zero."""
     deg = og.degree()
     hub = deg > d_rule
     hb = np.zeros(og.n + 1, dtype=np.int64)
     hb[1:] = np.cumsum(np.where(hub, deg, 0))
     rows = memo
-    assert rows.shape[0] >= hb[-1]
+    assert rows.shape[0] >= hb[-1] and rows.shape[1] == 128
     touched = np.nonzero(rows[:hb[-1]].any(axis=1))[0]
     rng = np.random.default_rng(seed)
     pick = touched if len(touched) <= limit else rng.choice(touched, limit, replace=False)
     hubs = np.nonzero(hub)[0]
     owner = hubs[np.searchsorted(hb[hubs], pick, side="right") - 1]
+    hinted = 0
     for r, v in zip(pick, owner):
         pos = int(r - hb[v])
         nv = og.row(v)
         t = int(nv[pos])
+        nt = og.row(t)
         seglen, nsup = sketch_segments(int(deg[v]))
-        com = np.isin(nv, og.row(t), assume_unique=True)
-        want = np.add.reduceat(com.astype(np.int64), np.arange(0, len(nv), seglen)) + 1
-        got = rows[r]
+        com = np.isin(nv, nt, assume_unique=True)
+        firsts = np.arange(0, len(nv), seglen)
+        want = np.add.reduceat(com.astype(np.int64), firsts) + 1
+        got = rows[r, :64]
         assert np.array_equal(got[:nsup], want), (int(v), t, got[:nsup], want)
-        assert not got[nsup:].any(), (int(v), t)
+        assert not got[nsup:].any() and not rows[r, 64 + nsup:].any(), (int(v), t)
+        hs = hint_shift(len(nt))
+        lb = np.searchsorted(nt, nv[firsts], side="left")
+        ub_prev = np.concatenate([[0], np.searchsorted(nt, nv[firsts[1:] - 1], side="right")])
+        h = rows[r, 64:64 + nsup].astype(np.int64)
+        known = h > 0
+        hinted += int(known.sum())
+        assert np.all((ub_prev >> hs)[known] <= h[known] - 1), (int(v), t)
+        assert np.all(h[known] - 1 <= (lb >> hs)[known]), (int(v), t)
+    assert hinted > 0
     return len(touched)
 
 
-@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
-def test_pair_sketch_contents(mode):
+@pytest.mark.parametrize("mode,t_wg", [(P.MODE_PERSISTENT, 8192), (P.MODE_PLAIN, 8192), (P.MODE_PLAIN, 0)])
+def test_pair_sketch_contents(mode, t_wg):
     # the sketches written during a call (by forward merges and by the reverse pairs they also
     # count) hold exact per-segment common-neighbour counts
     import torch
@@ -272,9 +323,9 @@ def test_pair_sketch_contents(mode):
     deg = og.degree()
     hubs = np.argsort(deg)[-256:].astype(np.uint32)
     starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
-    got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=100000)
+    got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=100000, t_wg=t_wg)
     torch.cuda.synchronize()
-    memo = g.memo.cpu().numpy().view(np.uint16).reshape(-1, 64)
+    memo = g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128)
     n = check_sketch_rows(og, memo, 40)
     say(f"[walk] sketches mode={mode}: {n} rows written")
     assert n > 1000
