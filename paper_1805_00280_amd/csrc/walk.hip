@@ -53,7 +53,7 @@ constexpr int HCH = 512;            // weighted scan chunk: 8 entries per lane
 constexpr int HEPL = HCH / WAVE;
 constexpr int TX = 512;             // dense merge: N(v) tile, 8 entries per lane
 constexpr int XPL = TX / WAVE;
-constexpr int YPL = 16;             // dense merge: N(t) block of 16 x 64 entries
+constexpr int YPL = 8;              // dense merge: later N(t) blocks of 8 x 64 entries
 constexpr int YFIRST = 4;           // entries per lane of the first N(t) block of a tile
 constexpr int NSUPER = MEMO_SEGS;   // segments (sums) per hub row
 constexpr int SPCAP = 512;          // specials held by the sparse path
@@ -224,9 +224,6 @@ __device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, uin
 }
 
 // ------------------------------------------------------------------ hubs
-// Flags the tile entries equal to a block of NB x 64 entries of N(t) loaded
-// from ypos; returns how many block entries lie in the tile's value range
-// (they form a prefix of the block, N(t) being sorted).
 // Sketch rows: MEMO_SEGS counts (one plus the number of members of N(t) in
 // a segment of N(v); 0 = unknown), then MEMO_SEGS start hints: hint h > 0 of a
 // segment says that its merge may start streaming N(t) at index
@@ -250,29 +247,43 @@ struct RevSketch {
 
 // Flags the tile entries equal to a block of NB x 64 entries of N(t) loaded
 // from ypos; returns how many block entries lie in the tile's value range
-// (they form a prefix of the block, N(t) being sorted).
+// (they form a prefix of the block, N(t) being sorted).  The lower bounds in
+// the tile are found by branchless searches that advance SEARCH_ILP entries
+// per lane in lockstep, so their LDS reads overlap instead of each probe
+// waiting for the previous one.
+constexpr int SEARCH_ILP = 4;
+
 template <int NB>
 __device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB], uint32_t ypos, uint32_t td,
                                                uint32_t j0, uint32_t cnt, uint32_t xlast, const RevSketch &R)
 {
+    static_assert(NB % SEARCH_ILP == 0, "blocks are searched SEARCH_ILP entries per lane at a time");
     const int l = lane_id();
     uint32_t nin = 0;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const uint32_t idx = ypos + b * WAVE + l;
-        const bool in = idx < td && y[b] <= xlast;
-        nin += __popcll(ballot(in));
-        if (in) {  // branchless search over the padded tile: pos = entries below y
-            uint32_t pos = 0;
+    for (int b = 0; b < NB; ++b) nin += __popcll(ballot(ypos + b * WAVE + l < td && y[b] <= xlast));
 #pragma unroll
-            for (uint32_t step = TX / 2; step >= 1; step >>= 1)
-                if (L.a.d.xs[pos + step - 1] < y[b]) pos += step;
-            const bool hit = pos < cnt && L.a.d.xs[pos] == y[b];
-            if (hit) L.a.d.flag[pos] = 1;
-            if (R.rseg && (hit || (idx & (TX - 1)) == 0)) {
-                const uint32_t k = idx / R.rseg;
-                if (hit) atomicAdd(&R.rc[k], 1u);
-                if (idx == k * R.rseg) R.rh[k] = ((j0 + pos) >> R.shift) + 1;
+    for (int g = 0; g < NB; g += SEARCH_ILP) {
+        if ((uint32_t)(g * WAVE) >= nin) break;  // the rest of the block lies beyond the tile
+        uint32_t pos[SEARCH_ILP];
+#pragma unroll
+        for (int k = 0; k < SEARCH_ILP; ++k) pos[k] = 0;
+#pragma unroll
+        for (uint32_t step = TX / 2; step >= 1; step >>= 1) {
+#pragma unroll
+            for (int k = 0; k < SEARCH_ILP; ++k)
+                pos[k] += L.a.d.xs[pos[k] + step - 1] < y[g + k] ? step : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < SEARCH_ILP; ++k) {
+            const uint32_t idx = ypos + (g + k) * WAVE + l;
+            const bool in = idx < td && y[g + k] <= xlast;
+            const bool hit = in && pos[k] < cnt && L.a.d.xs[pos[k]] == y[g + k];
+            if (hit) L.a.d.flag[pos[k]] = 1;
+            if (R.rseg && in && (hit || (idx & (TX - 1)) == 0)) {
+                const uint32_t q = idx / R.rseg;
+                if (hit) atomicAdd(&R.rc[q], 1u);
+                if (idx == q * R.rseg) R.rh[q] = ((j0 + pos[k]) >> R.shift) + 1;
             }
         }
     }
