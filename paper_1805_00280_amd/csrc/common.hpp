@@ -130,15 +130,44 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m)
     return join64(hi, lo);
 }
 
-// Inclusive prefix sum over the 64 lanes.
+// Lane l - (shift) within its row of 16 (row_shr), or the last lane of the
+// previous row (row_bcast:15) / of lanes 0..31 (row_bcast:31), by DPP; lanes
+// the pattern leaves out, or whose rows are masked off, read 0.  These are
+// register-to-register moves, with none of the LDS latency of a permute.
+// They read every lane's register, so callers keep all 64 lanes active.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint32_t dpp0(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, true);
+}
+
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint64_t dpp0_64(uint64_t v)
+{
+    return join64(dpp0<CTRL, ROWS>((uint32_t)(v >> 32)), dpp0<CTRL, ROWS>((uint32_t)v));
+}
+
+// Inclusive prefix sums over the 64 lanes (Hillis-Steele within rows of 16,
+// then the row totals carried across rows).
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v)
+{
+    v += dpp0<0x111>(v);        // row_shr:1
+    v += dpp0<0x112>(v);        // row_shr:2
+    v += dpp0<0x114>(v);        // row_shr:4
+    v += dpp0<0x118>(v);        // row_shr:8
+    v += dpp0<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp0<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v)
 {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint64_t o = shfl_up64(v, d);
-        if (l >= d) v += o;
-    }
+    v += dpp0_64<0x111>(v);
+    v += dpp0_64<0x112>(v);
+    v += dpp0_64<0x114>(v);
+    v += dpp0_64<0x118>(v);
+    v += dpp0_64<0x142, 0xa>(v);
+    v += dpp0_64<0x143, 0xc>(v);
     return v;
 }
 
@@ -158,19 +187,9 @@ __device__ __forceinline__ uint64_t lane_val64(uint64_t v, int src)
     return join64(__builtin_amdgcn_readlane((uint32_t)(v >> 32), src), __builtin_amdgcn_readlane((uint32_t)v, src));
 }
 
-__device__ __forceinline__ uint64_t wave_sum(uint64_t v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor64(v, m);
-    return uni64(v);
-}
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) { return lane_val64(wave_incl_scan(v), WAVE - 1); }
 
-__device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
-    return uni(v);
-}
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) { return lane_val(wave_incl_scan32(v), WAVE - 1); }
 
 __device__ __forceinline__ int first_lane(uint64_t mask) { return __ffsll((unsigned long long)mask) - 1; }
 

@@ -53,6 +53,7 @@ constexpr int HCH = 512;            // weighted scan chunk: 8 entries per lane
 constexpr int HEPL = HCH / WAVE;
 constexpr int TX = 512;             // dense merge: N(v) tile, 8 entries per lane
 constexpr int XPL = TX / WAVE;
+static_assert(XPL == 8, "a lane's run of tile flags is read as one u64");
 constexpr int YPL = 8;              // dense merge: later N(t) blocks of 8 x 64 entries
 constexpr int YFIRST = 4;           // entries per lane of the first N(t) block of a tile
 constexpr int NSUPER = MEMO_SEGS;   // segments (sums) per hub row
@@ -311,10 +312,8 @@ __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *
         y0[b] = idx < td ? Y[idx] : 0xFFFFFFFFu;
     }
 #pragma unroll
-    for (int e = 0; e < XPL; ++e) {
-        L.a.d.xs[e * WAVE + l] = xv[e];
-        L.a.d.flag[e * WAVE + l] = 0;
-    }
+    for (int e = 0; e < XPL; ++e) L.a.d.xs[e * WAVE + l] = xv[e];
+    *(uint64_t *)&L.a.d.flag[l * XPL] = 0;
     wave_lds_sync();
     const uint32_t xlast = L.a.d.xs[cnt - 1];
     uint32_t nin = flag_block<YFIRST>(L, y0, ypos, td, j0, cnt, xlast, R);
@@ -333,10 +332,9 @@ __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *
         }
     }
     wave_lds_sync();
-    uint32_t c = 0;
-#pragma unroll
-    for (int e = 0; e < XPL; ++e) c += L.a.d.flag[e * WAVE + l];
-    return wave_sum32(c);
+    // flags are 0/1 bytes: the byte sum of the lane's eight
+    const uint64_t f8 = *(const uint64_t *)&L.a.d.flag[l * XPL];
+    return wave_sum32((uint32_t)((f8 * 0x0101010101010101ull) >> 56));
 }
 
 // pi of entry j0+i of a tile (weights from W, or 1).
@@ -362,21 +360,43 @@ __device__ uint64_t dense_chunk_sum(const uint16_t *__restrict__ W, const JobCtx
 }
 
 // First index of the tile whose running prefix (base + partial) exceeds r,
-// or SENT (base then holds the prefix after the tile).
+// or SENT (base then holds the prefix after the tile).  Lane l takes the run
+// of entries [XPL*l, XPL*l + XPL): one 32-bit wave scan of the run sums (a
+// tile sums to at most 512 * 65535 * 16 < 2^32) finds the lane whose run
+// crosses r, and that lane walks its run.
 __device__ uint32_t dense_chunk_locate(const uint16_t *__restrict__ W, const JobCtx &J, uint32_t pos_t,
                                        const HubLds &L, uint32_t j0, uint32_t cnt, uint64_t &base, uint64_t r)
 {
     const int l = lane_id();
-#pragma unroll 1
+    const uint32_t i0 = (uint32_t)l * XPL;
+    const uint64_t f8 = *(const uint64_t *)&L.a.d.flag[i0];
+    uint32_t pi[XPL];
+    uint32_t run = 0;
+#pragma unroll
     for (int e = 0; e < XPL; ++e) {
-        const uint32_t i = e * WAVE + l;
-        const uint64_t pi = i < cnt ? dense_pi(W, J, pos_t, L, j0, i) : 0;
-        const uint64_t inc = wave_incl_scan(pi);
-        const uint64_t m = ballot(i < cnt && base + inc > r);
-        if (m) return j0 + e * WAVE + first_lane(m);
-        base += lane_val64(inc, WAVE - 1);
+        const uint32_t i = i0 + e;
+        const uint32_t w = i < cnt ? (W ? W[j0 + i] : 1u) : 0u;
+        const uint32_t m = (j0 + i == pos_t) ? J.A_ret : (((f8 >> (8 * e)) & 0xFF) ? A_COM : J.A_out);
+        pi[e] = w * m;
+        run += pi[e];
     }
-    return SENT;
+    const uint32_t inc = wave_incl_scan32(run);
+    const uint64_t m = ballot(base + inc > r);
+    if (m == 0) {
+        base += lane_val(inc, WAVE - 1);
+        return SENT;
+    }
+    const int f = first_lane(m);
+    uint32_t j = SENT;
+    if (l == f) {
+        uint64_t acc = base + (inc - run);
+#pragma unroll
+        for (int e = 0; e < XPL; ++e) {
+            acc += pi[e];
+            if (j == SENT && acc > r) j = j0 + i0 + e;
+        }
+    }
+    return lane_val(j, f);
 }
 
 // Sum of pi over N(v)[j0, j0+len) of an unweighted row with c members of N(t).
