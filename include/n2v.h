@@ -52,7 +52,7 @@ extern "C" {
 #endif
 
 #define N2V_SENT 0xFFFFFFFFu
-#define N2V_ABI_VERSION 2
+#define N2V_ABI_VERSION 3
 
 enum {
     N2V_OK = 0,
@@ -157,6 +157,10 @@ typedef struct {
     uint32_t t_wg;       /* plain: dense hub moves at degree > max(t_wg, d_rule) are evaluated by
                             a whole workgroup (its wavefronts split the merge), the others by one
                             wavefront each (default 8192) */
+    uint32_t search_ratio; /* dense hub moves look N(v)'s entries up in N(t) (pivots in LDS, then
+                            a search in one bucket) instead of streaming N(t) when the part of
+                            N(t) to stream is more than search_ratio times longer (default 2;
+                            0: always look up) */
 } n2v_exec_opts;
 
 /* Fills execution defaults (tuned values when an autotune result was stored

@@ -54,7 +54,8 @@ class GraphOpts(C.Structure):
 class ExecOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("t_wave", C.c_uint32), ("t_sparse", C.c_uint32),
                 ("sparse_ratio", C.c_uint32), ("waves_per_cu", C.c_uint32), ("block", C.c_uint32),
-                ("memo", C.c_uint32), ("t_wg", C.c_uint32)]
+                ("memo", C.c_uint32), ("t_wg", C.c_uint32),
+                ("search_ratio", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,7 +76,7 @@ class Result(C.Structure):
                 ("start_ns", C.c_uint64), ("done_ns", C.c_uint64)]
 
 
-ABI_VERSION = 2  # layout of the option structs below
+ABI_VERSION = 3  # layout of the option structs below
 _lib = None
 
 

@@ -3,7 +3,8 @@
 // It times the persistent kernel on a seeded sample of walks (start vertices
 // drawn uniformly over all vertices, the same distribution as walks from
 // every vertex) under candidate settings of the degree thresholds, the
-// sparse/dense hub cost weight and the grid size, by coordinate descent, and
+// sparse/dense hub cost weight, the grid size and the stream/search switch of
+// dense merges, by coordinate descent, and
 // stores the fastest setting in the graph.  Execution parameters never change
 // outputs, so tuning cannot change any result.
 #include <vector>
@@ -105,14 +106,16 @@ extern "C" int n2v_autotune(n2v_graph *g, uint32_t n_walks, uint32_t L, float p,
     const uint32_t t_wave_c[] = {0, 8, 32, 64, 128, 256, 1024};
     const uint32_t ratio_c[] = {1, 2, 4, 8, 16};
     const uint32_t waves_c[] = {0, 8, 12, 16};
-    for (int pass = 0; pass < 3; ++pass) {
-        const uint32_t *vals = pass == 0 ? t_wave_c : pass == 1 ? ratio_c : waves_c;
-        const int nv = pass == 0 ? 7 : pass == 1 ? 5 : 4;
+    const uint32_t search_c[] = {0, 1, 2, 4, 16, 0xFFFFFFFFu};
+    for (int pass = 0; pass < 4; ++pass) {
+        const uint32_t *vals = pass == 0 ? t_wave_c : pass == 1 ? ratio_c : pass == 2 ? waves_c : search_c;
+        const int nv = pass == 0 ? 7 : pass == 1 ? 5 : pass == 2 ? 4 : 6;
         for (int i = 0; i < nv; ++i) {
             n2v_exec_opts o = cur;
             if (pass == 0) o.t_wave = vals[i];
             if (pass == 1) o.sparse_ratio = vals[i];
             if (pass == 2) o.waves_per_cu = vals[i];
+            if (pass == 3) o.search_ratio = vals[i];
             double ms = 0;
             rc = run(o, &ms);
             if (rc) return rc;

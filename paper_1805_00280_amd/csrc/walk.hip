@@ -58,8 +58,9 @@ constexpr int YPL = 8;              // dense merge: later N(t) blocks of 8 x 64 
 constexpr int YFIRST = 4;           // entries per lane of the first N(t) block of a tile
 constexpr int NSUPER = MEMO_SEGS;   // segments (sums) per hub row
 constexpr int SPCAP = 512;          // specials held by the sparse path
+constexpr int NPIV = 512;           // pivots of an N(t) range that N(v) entries are searched in
 
-// LDS of one wavefront for hub moves (6 KiB).
+// LDS of one wavefront for hub moves (8 KiB).
 struct HubLds {
     union {
         struct {
@@ -77,6 +78,7 @@ struct HubLds {
         uint64_t csum[NSUPER];
         int32_t dl[HCH];
     } b;
+    uint32_t piv[NPIV];  // pivots for searching N(v) entries in N(t)
 };
 
 // Lower bound of x in row[0, n) found by the whole wavefront: each round the
@@ -337,6 +339,82 @@ __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *
     return wave_sum32((uint32_t)((f8 * 0x0101010101010101ull) >> 56));
 }
 
+// Pivots of Y[ylo, yhi) in LDS: bucket k is Y[ylo + kB, min(ylo + (k+1)B, yhi))
+// with B = ceil((yhi - ylo) / NPIV), and piv[k] is its last entry (0xFFFFFFFF
+// for an empty bucket), so the only bucket that can hold a value x is the
+// first k with piv[k] >= x.  Returns B.
+__device__ uint32_t load_pivots(const uint32_t *__restrict__ Y, uint32_t ylo, uint32_t yhi, HubLds &L)
+{
+    const int l = lane_id();
+    const uint32_t ny = yhi - ylo;
+    const uint32_t B = (ny + NPIV - 1) / NPIV;
+#pragma unroll
+    for (int e = 0; e < NPIV / WAVE; ++e) {
+        const uint32_t k = e * WAVE + l;
+        const uint64_t lo = (uint64_t)k * B, hi = lo + B < ny ? lo + B : ny;
+        L.piv[k] = lo < ny ? Y[ylo + hi - 1] : 0xFFFFFFFFu;
+    }
+    wave_lds_sync();
+    return B;
+}
+
+// Flags the members of N(t) in the tile N(v)[j0, j0+cnt) by searching each
+// entry in Y[ylo, yhi) (which must hold every match; pivots of B entries per
+// bucket in LDS): a lockstep LDS search over the pivots, then a branchless
+// search inside the bucket, SEARCH_ILP entries per lane at a time.  Returns
+// the number flagged; lb0 receives the lower bound in N(t) of the tile's first
+// entry.  Matches are also counted in R.rc (reverse start hints stay unknown).
+__device__ uint32_t search_flags(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y, uint32_t ylo,
+                                 uint32_t yhi, uint32_t B, HubLds &L, uint32_t j0, uint32_t cnt, const RevSketch &R,
+                                 uint32_t &lb0)
+{
+    const int l = lane_id();
+    uint32_t c = 0, first = yhi;
+#pragma unroll
+    for (int h = 0; h < XPL; h += SEARCH_ILP) {
+        uint32_t x[SEARCH_ILP], p[SEARCH_ILP];
+#pragma unroll
+        for (int k = 0; k < SEARCH_ILP; ++k) {
+            const uint32_t i = (h + k) * WAVE + l;
+            x[k] = i < cnt ? X[j0 + i] : 0xFFFFFFFFu;
+            p[k] = 0;
+        }
+#pragma unroll
+        for (uint32_t step = NPIV / 2; step >= 1; step >>= 1) {
+#pragma unroll
+            for (int k = 0; k < SEARCH_ILP; ++k) p[k] += L.piv[p[k] + step - 1] < x[k] ? step : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < SEARCH_ILP; ++k) {
+            p[k] += L.piv[p[k]] < x[k] ? 1u : 0u;  // bucket index, NPIV past the last
+            const uint64_t b0 = (uint64_t)ylo + (uint64_t)p[k] * B;
+            p[k] = b0 < yhi ? (uint32_t)b0 : yhi;
+        }
+        // the lower bound lies in [p, p + len - 1]; probes past yhi read as +inf
+        for (uint32_t len = B; len > 1; len -= len >> 1) {
+            const uint32_t half = len >> 1;
+#pragma unroll
+            for (int k = 0; k < SEARCH_ILP; ++k) {
+                const uint32_t q = p[k] + half - 1;
+                const uint32_t v = q < yhi ? Y[q] : 0xFFFFFFFFu;
+                p[k] += v < x[k] ? half : 0u;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < SEARCH_ILP; ++k) {
+            const uint32_t i = (h + k) * WAVE + l;
+            const bool hit = i < cnt && p[k] < yhi && Y[p[k]] == x[k];
+            L.a.d.flag[i] = hit ? 1 : 0;
+            c += hit ? 1u : 0u;
+            if (R.rseg && hit) atomicAdd(&R.rc[p[k] / R.rseg], 1u);
+            if (h + k == 0) first = p[k];
+        }
+    }
+    lb0 = lane_val(first, 0);
+    wave_lds_sync();
+    return wave_sum32(c);
+}
+
 // pi of entry j0+i of a tile (weights from W, or 1).
 __device__ __forceinline__ uint64_t dense_pi(const uint16_t *__restrict__ W, const JobCtx &J, uint32_t pos_t,
                                              const HubLds &L, uint32_t j0, uint32_t i)
@@ -446,12 +524,18 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     uint16_t *row = nullptr;
     if (E.g.memo && !W && pos_t != SENT && dv > E.g.d_rule) row = sketch_row(E, st.v, pos_t);
     bool warm = false;
-    uint32_t known = 1, ystart = SENT;  // per segment (lane): count + 1, start of N(t) or SENT
+    // per segment (lane): count + 1; where its stream of N(t) may start (SENT:
+    // unknown), and an index at or above that start
+    uint32_t known = 1, ystart = SENT, ycap = td;
     if (row) {
         if ((uint32_t)l < nsup) {
             known = row[l];
             const uint32_t h = row[MEMO_SEGS + l];
-            if (h) ystart = (h - 1) << hs;
+            if (h) {
+                ystart = (h - 1) << hs;
+                const uint64_t up = (uint64_t)h << hs;
+                ycap = up < td ? (uint32_t)up : td;
+            }
         }
         warm = ballot(known == 0) == 0;
     }
@@ -473,7 +557,11 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             L.a.d.rc[l] = 0;
             L.a.d.rh[l] = 0;
         }
-        uint32_t ypos = td ? wave_lower_bound(Y, td, X[0]) : 0;
+        // N(t) much longer than N(v): search N(v)'s entries in it instead of
+        // streaming it (reverse start hints then stay unknown)
+        const bool srch = (uint64_t)td > (uint64_t)E.search_ratio * dv;
+        const uint32_t B = srch ? load_pivots(Y, 0, td, L) : 0;
+        uint32_t ypos = !srch && td ? wave_lower_bound(Y, td, X[0]) : 0;
         uint32_t mine = 0;
         S = 0;
         for (uint32_t sp = 0; sp < nsup; ++sp) {
@@ -484,7 +572,14 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             for (uint32_t sub = sp * G; sub < sub_end; ++sub) {
                 const uint32_t j0 = sub * TX;
                 const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
-                const uint32_t c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
+                uint32_t c;
+                if (srch) {
+                    uint32_t lb0;
+                    c = search_flags(X, Y, 0, td, B, L, j0, cnt, R, lb0);
+                    if (sub == sp * G && (uint32_t)l == sp) ystart = lb0;
+                } else {
+                    c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
+                }
                 sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, c);
                 csp += c;
                 wave_lds_sync();
@@ -497,6 +592,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
             __builtin_nontemporal_store((uint16_t)((ystart >> hs) + 1), row + MEMO_SEGS + l);
         }
+        ycap = ystart;
         const uint32_t rsup = R.rseg ? (td + R.rseg - 1) / R.rseg : 0;
         if (rrow && (uint32_t)l < rsup) {
             __builtin_nontemporal_store((uint16_t)(L.a.d.rc[l] + 1), rrow + l);
@@ -520,16 +616,28 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         }
     }
     wave_lds_sync();
+    // the matches of segment spx lie in N(t)[ypos, yend): from its start to
+    // (at or above) the next segment's start
     const uint32_t x0 = spx * seglen;
     uint32_t ypos = lane_val(ystart, (int)spx);
     if (ypos == SENT) ypos = td ? wave_lower_bound(Y, td, X[x0]) : 0;
     if (ypos > td) ypos = td;
+    uint32_t yend = spx + 1 < nsup ? lane_val(ycap, (int)spx + 1) : td;
+    if (yend < ypos) yend = ypos;
+    const uint32_t xlen = dv - x0 < seglen ? dv - x0 : seglen;
+    const bool srch = (uint64_t)(yend - ypos) > (uint64_t)E.search_ratio * xlen;
+    const uint32_t B = srch ? load_pivots(Y, ypos, yend, L) : 0;
     const RevSketch none = {0, 0, nullptr, nullptr};
     const uint32_t sub_end = nsub < (spx + 1) * G ? nsub : (spx + 1) * G;
     for (uint32_t sub = spx * G; sub < sub_end; ++sub) {
         const uint32_t j0 = sub * TX;
         const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
-        dense_flags(X, Y, td, L, j0, cnt, ypos, none);
+        if (srch) {
+            uint32_t lb0;
+            search_flags(X, Y, ypos, yend, B, L, j0, cnt, none, lb0);
+        } else {
+            dense_flags(X, Y, td, L, j0, cnt, ypos, none);
+        }
         const uint32_t j = dense_chunk_locate(W, J, pos_t, L, j0, cnt, base, r);
         wave_lds_sync();
         if (j != SENT) return j;
@@ -1397,6 +1505,7 @@ void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E)
     E->t_wave = o.t_wave;
     E->t_sparse = o.t_sparse;
     E->t_wg = o.t_wg < g->dg.d_rule ? g->dg.d_rule : o.t_wg;
+    E->search_ratio = o.search_ratio;
     E->sparse_ratio = o.sparse_ratio < 1 ? 1 : o.sparse_ratio;
 }
 
@@ -1445,6 +1554,7 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
     o->block = 256;
     o->memo = 1;
     o->t_wg = 8192;
+    o->search_ratio = 2;
 }
 
 extern "C" int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_t L, const n2v_exec_opts *opts,

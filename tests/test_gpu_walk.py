@@ -39,6 +39,8 @@ def test_scale12_workload_full_parity(c1, mode):
     dict(t_sparse=0), dict(waves_per_cu=4), dict(t_wave=0, sparse_ratio=1, waves_per_cu=1),
     dict(mode=P.MODE_PLAIN, t_wg=0), dict(mode=P.MODE_PLAIN, t_wg=0, sparse_ratio=100000),
     dict(mode=P.MODE_PLAIN, t_wg=1 << 31),
+    dict(search_ratio=0), dict(search_ratio=0xFFFFFFFF), dict(search_ratio=0, sparse_ratio=100000),
+    dict(mode=P.MODE_PLAIN, search_ratio=0, sparse_ratio=100000),
 ])
 def test_execution_options_do_not_change_results(opts):
     torch_cuda()
@@ -116,6 +118,10 @@ def test_big_hubs_dense_and_sparse_paths():
         say(f"[walk] big hubs ratio={ratio}")
         got = gpu_walk(g, starts, 12, 0.5, 2.0, 3, sparse_ratio=ratio)
         assert first_mismatch(got, want) is None, first_mismatch(got, want)
+        for search in (0, 0xFFFFFFFF):
+            say(f"[walk] big hubs ratio={ratio} search_ratio={search}")
+            got = gpu_walk(g, starts, 12, 0.5, 2.0, 3, sparse_ratio=ratio, search_ratio=search)
+            assert first_mismatch(got, want) is None, first_mismatch(got, want)
         # plain form, every dense hub move evaluated by a whole workgroup
         say(f"[walk] big hubs ratio={ratio} workgroup class")
         got = gpu_walk(g, starts, 12, 0.5, 2.0, 3, sparse_ratio=ratio, mode=P.MODE_PLAIN, t_wg=0)
@@ -137,10 +143,11 @@ def test_workgroup_hub_class(weighted, memo):
     starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
     pq = (1.0, 0.5) if weighted else (0.25, 4.0)
     want = oracle_walk(og, starts, 25, *pq, 31, d_rule=100)
-    for t_wg in (0, 400, 1 << 31):
-        say(f"[walk] workgroup class weighted={weighted} memo={memo} t_wg={t_wg}")
-        got = gpu_walk(g, starts, 25, *pq, 31, mode=P.MODE_PLAIN, t_wg=t_wg, sparse_ratio=100000, memo=memo)
-        assert first_mismatch(got, want) is None, (t_wg, first_mismatch(got, want))
+    for t_wg, search in ((0, 2), (400, 2), (1 << 31, 2), (0, 0), (0, 0xFFFFFFFF)):
+        say(f"[walk] workgroup class weighted={weighted} memo={memo} t_wg={t_wg} search={search}")
+        got = gpu_walk(g, starts, 25, *pq, 31, mode=P.MODE_PLAIN, t_wg=t_wg, sparse_ratio=100000, memo=memo,
+                       search_ratio=search)
+        assert first_mismatch(got, want) is None, (t_wg, search, first_mismatch(got, want))
     if memo and not weighted:
         torch.cuda.synchronize()
         n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128), 100)
@@ -311,8 +318,10 @@ def check_sketch_rows(og, memo, d_rule, limit=6000, seed=1):
     return len(touched)
 
 
-@pytest.mark.parametrize("mode,t_wg", [(P.MODE_PERSISTENT, 8192), (P.MODE_PLAIN, 8192), (P.MODE_PLAIN, 0)])
-def test_pair_sketch_contents(mode, t_wg):
+@pytest.mark.parametrize("mode,t_wg,search", [(P.MODE_PERSISTENT, 8192, 2), (P.MODE_PLAIN, 8192, 2),
+                                               (P.MODE_PLAIN, 0, 2), (P.MODE_PERSISTENT, 8192, 0),
+                                               (P.MODE_PERSISTENT, 8192, 0xFFFFFFFF)])
+def test_pair_sketch_contents(mode, t_wg, search):
     # the sketches written during a call (by forward merges and by the reverse pairs they also
     # count) hold exact per-segment common-neighbour counts
     import torch
@@ -323,7 +332,7 @@ def test_pair_sketch_contents(mode, t_wg):
     deg = og.degree()
     hubs = np.argsort(deg)[-256:].astype(np.uint32)
     starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
-    got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=100000, t_wg=t_wg)
+    got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=100000, t_wg=t_wg, search_ratio=search)
     torch.cuda.synchronize()
     memo = g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128)
     n = check_sketch_rows(og, memo, 40)
