@@ -149,7 +149,8 @@ enum { N2V_OUT_WALKS = 1, N2V_OUT_COUNTS = 2 };
 typedef struct {
     int mode;            /* N2V_MODE_*; AUTO = PERSISTENT */
     uint32_t t_wave;     /* persistent: rejection moves at degree > t_wave run wave-cooperatively */
-    uint32_t t_sparse;   /* hub moves use the sparse intersection when deg(t) <= t_sparse ... */
+    uint32_t t_sparse;   /* hub moves use the sparse intersection when deg(t) <= t_sparse (default
+                            1023, the most the sparse path holds) ... */
     uint32_t sparse_ratio; /* ... and deg(t) * sparse_ratio * log2(deg v) < deg(v) + deg(t) */
     uint32_t waves_per_cu; /* persistent grid size (0: occupancy-derived) */
     uint32_t block;      /* workgroup size (256) */
@@ -159,7 +160,7 @@ typedef struct {
                             wavefront each (default 8192) */
     uint32_t search_ratio; /* dense hub moves look N(v)'s entries up in N(t) (pivots in LDS, then
                             a search in one bucket) instead of streaming N(t) when the part of
-                            N(t) to stream is more than search_ratio times longer (default 2;
+                            N(t) to stream is more than search_ratio times longer (default 4;
                             0: always look up) */
 } n2v_exec_opts;
 

@@ -104,7 +104,7 @@ extern "C" int n2v_autotune(n2v_graph *g, uint32_t n_walks, uint32_t L, float p,
     int rc = run(cur, &cur_ms);
     if (rc) return rc;
     const uint32_t t_wave_c[] = {0, 8, 32, 64, 128, 256, 1024};
-    const uint32_t ratio_c[] = {1, 2, 4, 8, 16};
+    const uint32_t ratio_c[] = {2, 4, 8, 16, 32};
     const uint32_t waves_c[] = {0, 8, 12, 16};
     const uint32_t search_c[] = {0, 1, 2, 4, 16, 0xFFFFFFFFu};
     for (int pass = 0; pass < 4; ++pass) {

@@ -57,7 +57,7 @@ static_assert(XPL == 8, "a lane's run of tile flags is read as one u64");
 constexpr int YPL = 8;              // dense merge: later N(t) blocks of 8 x 64 entries
 constexpr int YFIRST = 4;           // entries per lane of the first N(t) block of a tile
 constexpr int NSUPER = MEMO_SEGS;   // segments (sums) per hub row
-constexpr int SPCAP = 512;          // specials held by the sparse path
+constexpr int SPCAP = 1024;         // specials (positions) held by the sparse path
 constexpr int NPIV = 512;           // pivots of an N(t) range that N(v) entries are searched in
 
 // LDS of one wavefront for hub moves (8 KiB).
@@ -71,7 +71,6 @@ struct HubLds {
         } d;
         struct {
             uint32_t pos[SPCAP];
-            int32_t del[SPCAP];
         } sp;
     } a;
     union {
@@ -339,23 +338,44 @@ __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *
     return wave_sum32((uint32_t)((f8 * 0x0101010101010101ull) >> 56));
 }
 
-// Pivots of Y[ylo, yhi) in LDS: bucket k is Y[ylo + kB, min(ylo + (k+1)B, yhi))
-// with B = ceil((yhi - ylo) / NPIV), and piv[k] is its last entry (0xFFFFFFFF
-// for an empty bucket), so the only bucket that can hold a value x is the
-// first k with piv[k] >= x.  Returns B.
-__device__ uint32_t load_pivots(const uint32_t *__restrict__ Y, uint32_t ylo, uint32_t yhi, HubLds &L)
+// np (a power of two, 64..NPIV) pivots of Y[ylo, yhi) in LDS: bucket k is
+// Y[ylo + kB, min(ylo + (k+1)B, yhi)) with B = ceil((yhi - ylo) / np), and
+// piv[k] is its last entry (0xFFFFFFFF for an empty bucket), so the only
+// bucket that can hold a value x is the first k with piv[k] >= x.  Returns B.
+__device__ uint32_t load_pivots(const uint32_t *__restrict__ Y, uint32_t ylo, uint32_t yhi, HubLds &L, uint32_t np)
 {
     const int l = lane_id();
     const uint32_t ny = yhi - ylo;
-    const uint32_t B = (ny + NPIV - 1) / NPIV;
-#pragma unroll
-    for (int e = 0; e < NPIV / WAVE; ++e) {
-        const uint32_t k = e * WAVE + l;
+    const uint32_t B = (ny + np - 1) / np;
+    for (uint32_t k = l; k < np; k += WAVE) {
         const uint64_t lo = (uint64_t)k * B, hi = lo + B < ny ? lo + B : ny;
         L.piv[k] = lo < ny ? Y[ylo + hi - 1] : 0xFFFFFFFFu;
     }
     wave_lds_sync();
     return B;
+}
+
+// Pivot count for searching n values: about one per value, 64..NPIV.
+__device__ __forceinline__ uint32_t pivots_for(uint32_t n)
+{
+    uint32_t np = WAVE;
+    while (np < (uint32_t)NPIV && np < n) np <<= 1;
+    return np;
+}
+
+// Bucket of x among np pivots (number of pivots below x, 0..np), SEARCH_ILP
+// values per lane in lockstep.
+__device__ __forceinline__ void pivot_buckets(const HubLds &L, uint32_t np, const uint32_t (&x)[SEARCH_ILP],
+                                              uint32_t (&p)[SEARCH_ILP])
+{
+#pragma unroll
+    for (int k = 0; k < SEARCH_ILP; ++k) p[k] = 0;
+    for (uint32_t step = np >> 1; step >= 1; step >>= 1) {
+#pragma unroll
+        for (int k = 0; k < SEARCH_ILP; ++k) p[k] += L.piv[p[k] + step - 1] < x[k] ? step : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < SEARCH_ILP; ++k) p[k] += L.piv[p[k]] < x[k] ? 1u : 0u;
 }
 
 // Flags the members of N(t) in the tile N(v)[j0, j0+cnt) by searching each
@@ -365,8 +385,8 @@ __device__ uint32_t load_pivots(const uint32_t *__restrict__ Y, uint32_t ylo, ui
 // the number flagged; lb0 receives the lower bound in N(t) of the tile's first
 // entry.  Matches are also counted in R.rc (reverse start hints stay unknown).
 __device__ uint32_t search_flags(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y, uint32_t ylo,
-                                 uint32_t yhi, uint32_t B, HubLds &L, uint32_t j0, uint32_t cnt, const RevSketch &R,
-                                 uint32_t &lb0)
+                                 uint32_t yhi, uint32_t np, uint32_t B, HubLds &L, uint32_t j0, uint32_t cnt,
+                                 const RevSketch &R, uint32_t &lb0)
 {
     const int l = lane_id();
     uint32_t c = 0, first = yhi;
@@ -377,16 +397,10 @@ __device__ uint32_t search_flags(const uint32_t *__restrict__ X, const uint32_t 
         for (int k = 0; k < SEARCH_ILP; ++k) {
             const uint32_t i = (h + k) * WAVE + l;
             x[k] = i < cnt ? X[j0 + i] : 0xFFFFFFFFu;
-            p[k] = 0;
         }
-#pragma unroll
-        for (uint32_t step = NPIV / 2; step >= 1; step >>= 1) {
-#pragma unroll
-            for (int k = 0; k < SEARCH_ILP; ++k) p[k] += L.piv[p[k] + step - 1] < x[k] ? step : 0u;
-        }
+        pivot_buckets(L, np, x, p);  // bucket index, np past the last
 #pragma unroll
         for (int k = 0; k < SEARCH_ILP; ++k) {
-            p[k] += L.piv[p[k]] < x[k] ? 1u : 0u;  // bucket index, NPIV past the last
             const uint64_t b0 = (uint64_t)ylo + (uint64_t)p[k] * B;
             p[k] = b0 < yhi ? (uint32_t)b0 : yhi;
         }
@@ -560,7 +574,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         // N(t) much longer than N(v): search N(v)'s entries in it instead of
         // streaming it (reverse start hints then stay unknown)
         const bool srch = (uint64_t)td > (uint64_t)E.search_ratio * dv;
-        const uint32_t B = srch ? load_pivots(Y, 0, td, L) : 0;
+        const uint32_t B = srch ? load_pivots(Y, 0, td, L, NPIV) : 0;
         uint32_t ypos = !srch && td ? wave_lower_bound(Y, td, X[0]) : 0;
         uint32_t mine = 0;
         S = 0;
@@ -575,7 +589,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
                 uint32_t c;
                 if (srch) {
                     uint32_t lb0;
-                    c = search_flags(X, Y, 0, td, B, L, j0, cnt, R, lb0);
+                    c = search_flags(X, Y, 0, td, NPIV, B, L, j0, cnt, R, lb0);
                     if (sub == sp * G && (uint32_t)l == sp) ystart = lb0;
                 } else {
                     c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
@@ -626,7 +640,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     if (yend < ypos) yend = ypos;
     const uint32_t xlen = dv - x0 < seglen ? dv - x0 : seglen;
     const bool srch = (uint64_t)(yend - ypos) > (uint64_t)E.search_ratio * xlen;
-    const uint32_t B = srch ? load_pivots(Y, ypos, yend, L) : 0;
+    const uint32_t B = srch ? load_pivots(Y, ypos, yend, L, NPIV) : 0;
     const RevSketch none = {0, 0, nullptr, nullptr};
     const uint32_t sub_end = nsub < (spx + 1) * G ? nsub : (spx + 1) * G;
     for (uint32_t sub = spx * G; sub < sub_end; ++sub) {
@@ -634,7 +648,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
         if (srch) {
             uint32_t lb0;
-            search_flags(X, Y, ypos, yend, B, L, j0, cnt, none, lb0);
+            search_flags(X, Y, ypos, yend, NPIV, B, L, j0, cnt, none, lb0);
         } else {
             dense_flags(X, Y, td, L, j0, cnt, ypos, none);
         }
@@ -645,9 +659,19 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     return dv - 1;  // not reached: the last prefix equals S > r
 }
 
+// Excess of special position q of N(v) over the out-multiplier:
+// (A - A_out) * w_q with A = A_ret at t's position, else A_com.
+__device__ __forceinline__ int32_t special_delta(const Exec &E, const JobCtx &J, const WS &st, uint32_t q)
+{
+    const int32_t w = E.g.wt ? (int32_t)E.g.wt[st.vo + q] : 1;
+    const int32_t mult = q == st.pos_t ? (int32_t)J.A_ret : (int32_t)A_COM;
+    return (mult - (int32_t)J.A_out) * w;
+}
+
 // Weighted scan with specials: pi_j = m0 * w_j + delta_j, the deltas of the
 // c specials (sorted positions, in LDS) scattered chunk by chunk.
-__device__ uint32_t weighted_scan_locate(const Exec &E, const WS &st, HubLds &L, uint32_t m0, uint32_t c, uint64_t r)
+__device__ uint32_t weighted_scan_locate(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, uint32_t m0,
+                                         uint32_t c, uint64_t r)
 {
     const int l = lane_id();
     const uint64_t dv = st.vd;
@@ -661,7 +685,7 @@ __device__ uint32_t weighted_scan_locate(const Exec &E, const WS &st, HubLds &L,
         while (kp < c) {
             const uint32_t k = kp + l;
             const bool in = k < c && L.a.sp.pos[k] < j0 + cnt;
-            if (in) L.b.dl[L.a.sp.pos[k] - j0] = L.a.sp.del[k];
+            if (in) L.b.dl[L.a.sp.pos[k] - j0] = special_delta(E, J, st, L.a.sp.pos[k]);
             const uint32_t n_in = __popcll(ballot(in));
             kp += n_in;
             if (n_in < WAVE) break;
@@ -686,79 +710,74 @@ __device__ uint32_t weighted_scan_locate(const Exec &E, const WS &st, HubLds &L,
 }
 
 // Sparse inverse CDF: the members of N(t) are searched in N(v); they and t
-// are the only entries whose multiplier differs from A_out.
+// are the only entries whose multiplier differs from A_out.  The search takes
+// SEARCH_ILP members per lane in lockstep: pivots of N(v) in LDS (about one
+// per member searched) give the bucket, a branchless search inside it the
+// position.
 __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, uint64_t R1)
 {
     const int l = lane_id();
-    const uint32_t *__restrict__ adj = E.g.adj;
-    const uint64_t vo = st.vo, dv = st.vd;
-    // 64 pivots (the last entry of 64 equal buckets of N(v)) in LDS; each
-    // search starts inside the one bucket that can hold its value
-    const uint64_t bsz = (dv + WAVE - 1) / WAVE;
-    uint32_t *piv = (uint32_t *)L.b.dl;
-    piv[l] = adj[std::min<uint64_t>(vo + (uint64_t)(l + 1) * bsz - 1, vo + dv - 1)];
-    wave_lds_sync();
-    uint32_t c = 0;
-    for (uint32_t b = 0; b < st.td; b += WAVE) {
-        const uint32_t idx = b + l;
-        const bool valid = idx < st.td;
-        bool found = false;
-        uint64_t p = 0;
-        const uint32_t y = valid ? adj[st.to + idx] : 0xFFFFFFFFu;
-        // bucket = number of pivots below y
-        uint32_t k = 0;
+    const uint32_t *__restrict__ X = E.g.adj + st.vo;
+    const uint32_t *__restrict__ Y = E.g.adj + st.to;
+    const uint32_t dv = st.vd, td = st.td;
+    const uint32_t np = pivots_for(td);
+    const uint32_t B = load_pivots(X, 0, dv, L, np);
+    uint32_t c = 0;  // members found so far, in order (N(t) sorted => positions sorted)
+    for (uint32_t b0 = 0; b0 < td; b0 += SEARCH_ILP * WAVE) {
+        uint32_t y[SEARCH_ILP], p[SEARCH_ILP];
 #pragma unroll
-        for (uint32_t step = WAVE / 2; step >= 1; step >>= 1)
-            if (piv[k + step - 1] < y) k += step;
-        if (k == WAVE - 1 && piv[WAVE - 1] < y) k = WAVE;
-        if (valid) {
-            const uint64_t lo = vo + (uint64_t)k * bsz;
-            const uint64_t hi = std::min<uint64_t>(lo + bsz, vo + dv);
-            p = lo < vo + dv ? lower_bound_g(adj, lo, hi, y) : vo + dv;
-            found = p < vo + dv && adj[p] == y;
+        for (int k = 0; k < SEARCH_ILP; ++k) {
+            const uint32_t idx = b0 + k * WAVE + l;
+            y[k] = idx < td ? Y[idx] : 0xFFFFFFFFu;
         }
-        const uint64_t m = ballot(found);
-        if (found) L.a.sp.pos[c + __popcll(m & lanemask_lt())] = (uint32_t)(p - vo);
-        c += __popcll(m);
+        pivot_buckets(L, np, y, p);
+#pragma unroll
+        for (int k = 0; k < SEARCH_ILP; ++k) {
+            const uint64_t s0 = (uint64_t)p[k] * B;
+            p[k] = s0 < dv ? (uint32_t)s0 : dv;
+        }
+        for (uint32_t len = B; len > 1; len -= len >> 1) {
+            const uint32_t half = len >> 1;
+#pragma unroll
+            for (int k = 0; k < SEARCH_ILP; ++k) {
+                const uint32_t q = p[k] + half - 1;
+                const uint32_t v = q < dv ? X[q] : 0xFFFFFFFFu;
+                p[k] += v < y[k] ? half : 0u;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < SEARCH_ILP; ++k) {
+            const bool found = b0 + k * WAVE + l < td && p[k] < dv && X[p[k]] == y[k];
+            const uint64_t m = ballot(found);
+            if (found) L.a.sp.pos[c + __popcll(m & lanemask_lt())] = p[k];
+            c += __popcll(m);
+        }
     }
     wave_lds_sync();
-    // insert t's own position (t is never a member of N(t))
+    // insert t's own position (t is never a member of N(t)): the positions
+    // above it move up by one, block by block from the top
     if (st.pos_t != SENT) {
-        uint32_t vals[SPCAP / WAVE];
         uint32_t nless = 0;
-#pragma unroll
-        for (int e = 0; e < SPCAP / WAVE; ++e) {
-            const uint32_t k = e * WAVE + l;
-            vals[e] = k < c ? L.a.sp.pos[k] : SENT;
-            nless += (k < c && vals[e] < st.pos_t);
-        }
+        for (uint32_t k = l; k < c; k += WAVE) nless += L.a.sp.pos[k] < st.pos_t ? 1u : 0u;
         nless = wave_sum32(nless);
-        wave_lds_sync();
-#pragma unroll
-        for (int e = 0; e < SPCAP / WAVE; ++e) {
-            const uint32_t k = e * WAVE + l;
-            if (k < c) L.a.sp.pos[k + (vals[e] > st.pos_t ? 1u : 0u)] = vals[e];
+        for (int32_t b = (int32_t)((c + WAVE - 1) / WAVE) - 1; b >= 0; --b) {
+            const uint32_t k = (uint32_t)b * WAVE + l;
+            const uint32_t v = k < c ? L.a.sp.pos[k] : 0u;
+            wave_lds_sync();
+            if (k < c && k >= nless) L.a.sp.pos[k + 1] = v;
+            wave_lds_sync();
         }
         if (l == 0) L.a.sp.pos[nless] = st.pos_t;
         c += 1;
         wave_lds_sync();
     }
-    // deltas pi_j - A_out * w_j and their sum
     int64_t dsum = 0;
-    for (uint32_t k = l; k < c; k += WAVE) {
-        const uint32_t p = L.a.sp.pos[k];
-        const int64_t w = E.g.wt ? E.g.wt[vo + p] : 1;
-        const int64_t mult = (p == st.pos_t) ? (int64_t)J.A_ret : (int64_t)A_COM;
-        const int32_t dl = (int32_t)((mult - (int64_t)J.A_out) * w);
-        L.a.sp.del[k] = dl;
-        dsum += dl;
-    }
+    for (uint32_t k = l; k < c; k += WAVE) dsum += special_delta(E, J, st, L.a.sp.pos[k]);
     dsum = (int64_t)wave_sum((uint64_t)dsum);
-    wave_lds_sync();
     const uint64_t W = E.g.wt ? E.g.wsum[st.v] : dv;
     const uint64_t S = (uint64_t)((int64_t)(J.A_out * W) + dsum);
     const uint64_t r = hi64(R1, S);
-    if (E.g.wt) return weighted_scan_locate(E, st, L, J.A_out, c, r);
+    if (E.g.wt) return weighted_scan_locate(E, J, st, L, J.A_out, c, r);
     // unweighted: between specials the prefix grows by A_out per entry
     int64_t D = 0;       // deltas of the specials before this block
     int64_t qprev = -1;  // position of the special before this block
@@ -766,7 +785,7 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
         const uint32_t k = b + l;
         const bool valid = k < c;
         const int64_t q = valid ? (int64_t)L.a.sp.pos[k] : 0;
-        const int64_t dl = valid ? (int64_t)L.a.sp.del[k] : 0;
+        const int64_t dl = valid ? (int64_t)special_delta(E, J, st, (uint32_t)q) : 0;
         const int64_t inc = (int64_t)wave_incl_scan((uint64_t)dl);
         const int64_t Dincl = D + inc;
         const bool cross = valid && (int64_t)J.A_out * (q + 1) + Dincl > (int64_t)r;
@@ -944,7 +963,7 @@ __device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx
     const uint64_t R1 = join64(rr.x, rr.y);
     if (st.s == 0) {
         if (!E.g.wt) return (uint32_t)hi64(R1, st.vd);
-        return weighted_scan_locate(E, st, L, 1u, 0u, hi64(R1, E.g.wsum[st.v]));
+        return weighted_scan_locate(E, J, st, L, 1u, 0u, hi64(R1, E.g.wsum[st.v]));
     }
     uint32_t j = use_sparse(E, st) ? hub_sparse(E, J, st, L, R1) : hub_dense(E, J, st, L, R1);
     if (j >= st.vd) {  // cannot happen for a correct rule; keeps every read inside the row
@@ -1548,13 +1567,13 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
     }
     o->mode = N2V_MODE_AUTO;
     o->t_wave = 64;
-    o->t_sparse = 511;
-    o->sparse_ratio = 2;
+    o->t_sparse = 1023;
+    o->sparse_ratio = 16;
     o->waves_per_cu = 0;
     o->block = 256;
     o->memo = 1;
     o->t_wg = 8192;
-    o->search_ratio = 2;
+    o->search_ratio = 4;
 }
 
 extern "C" int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_t L, const n2v_exec_opts *opts,
