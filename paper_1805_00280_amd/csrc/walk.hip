@@ -267,15 +267,19 @@ __device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB
 #pragma unroll
     for (int g = 0; g < NB; g += SEARCH_ILP) {
         if ((uint32_t)(g * WAVE) >= nin) break;  // the rest of the block lies beyond the tile
-        uint32_t pos[SEARCH_ILP];
+        // the probes walk LDS pointers, so each address is the pointer plus
+        // an immediate offset
+        const uint32_t *q[SEARCH_ILP];
 #pragma unroll
-        for (int k = 0; k < SEARCH_ILP; ++k) pos[k] = 0;
+        for (int k = 0; k < SEARCH_ILP; ++k) q[k] = L.a.d.xs;
 #pragma unroll
         for (uint32_t step = TX / 2; step >= 1; step >>= 1) {
 #pragma unroll
-            for (int k = 0; k < SEARCH_ILP; ++k)
-                pos[k] += L.a.d.xs[pos[k] + step - 1] < y[g + k] ? step : 0u;
+            for (int k = 0; k < SEARCH_ILP; ++k) q[k] += q[k][step - 1] < y[g + k] ? step : 0u;
         }
+        uint32_t pos[SEARCH_ILP];
+#pragma unroll
+        for (int k = 0; k < SEARCH_ILP; ++k) pos[k] = (uint32_t)(q[k] - L.a.d.xs);
 #pragma unroll
         for (int k = 0; k < SEARCH_ILP; ++k) {
             const uint32_t idx = ypos + (g + k) * WAVE + l;
@@ -368,14 +372,15 @@ __device__ __forceinline__ uint32_t pivots_for(uint32_t n)
 __device__ __forceinline__ void pivot_buckets(const HubLds &L, uint32_t np, const uint32_t (&x)[SEARCH_ILP],
                                               uint32_t (&p)[SEARCH_ILP])
 {
+    const uint32_t *q[SEARCH_ILP];
 #pragma unroll
-    for (int k = 0; k < SEARCH_ILP; ++k) p[k] = 0;
+    for (int k = 0; k < SEARCH_ILP; ++k) q[k] = L.piv;
     for (uint32_t step = np >> 1; step >= 1; step >>= 1) {
 #pragma unroll
-        for (int k = 0; k < SEARCH_ILP; ++k) p[k] += L.piv[p[k] + step - 1] < x[k] ? step : 0u;
+        for (int k = 0; k < SEARCH_ILP; ++k) q[k] += q[k][step - 1] < x[k] ? step : 0u;
     }
 #pragma unroll
-    for (int k = 0; k < SEARCH_ILP; ++k) p[k] += L.piv[p[k]] < x[k] ? 1u : 0u;
+    for (int k = 0; k < SEARCH_ILP; ++k) p[k] = (uint32_t)(q[k] - L.piv) + (q[k][0] < x[k] ? 1u : 0u);
 }
 
 // Flags the members of N(t) in the tile N(v)[j0, j0+cnt) by searching each
