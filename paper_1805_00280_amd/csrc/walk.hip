@@ -1063,7 +1063,7 @@ struct JobTable {
 // ---------------------------------------------------------- persistent
 constexpr int PBLOCK = 256;
 constexpr int THREAD_ITERS = 8;
-constexpr int POOL = 256;  // walks a wavefront claims per atomic
+constexpr int POOL = 256;  // most walks a wavefront claims per atomic
 
 // Walk slot of one lane, kept in LDS between the thread and wave phases so
 // that neither phase holds the other's registers.
@@ -1115,6 +1115,10 @@ __global__ __launch_bounds__(PBLOCK) void k_persistent(Exec E, Src S)
     const uint32_t total = S.total();
     const uint32_t tw = E.t_wave < E.g.d_rule ? E.t_wave : E.g.d_rule;
     uint32_t pool_next = 0, pool_end = 0;  // walks this wavefront has claimed but not started
+    // claims of up to POOL walks, but small enough that every wavefront of the
+    // grid gets some (wave-class moves of a wavefront's walks run one by one)
+    const uint32_t nwaves = gridDim.x * (PBLOCK / WAVE);
+    const uint32_t pool = total / nwaves < 1u ? 1u : (total / nwaves < (uint32_t)POOL ? total / nwaves : (uint32_t)POOL);
     bool exhausted = false;
     uint64_t csum = 0;
     sl[l].flags = 0;
@@ -1127,21 +1131,21 @@ __global__ __launch_bounds__(PBLOCK) void k_persistent(Exec E, Src S)
             bool pend = q.flags & SL_PEND;
             uint32_t cap = q.flags & SL_CAP;
             if (live) slot_to_ws(E, q, st);
-            // idle lanes start walks claimed from the global counter, POOL at a time
+            // idle lanes start walks claimed from the global counter, pool at a time
             for (;;) {
                 const uint64_t m = ballot(!live);
                 if (m == 0) break;
                 if (pool_next >= pool_end) {
                     if (exhausted) break;
                     uint32_t b = 0;
-                    if (l == 0) b = atomicAdd(S.cursor(), (uint32_t)POOL);
+                    if (l == 0) b = atomicAdd(S.cursor(), pool);
                     b = uni(b);
                     if (b >= total) {
                         exhausted = true;
                         break;
                     }
                     pool_next = b;
-                    pool_end = total - b < (uint32_t)POOL ? total : b + POOL;
+                    pool_end = total - b < pool ? total : b + pool;
                 }
                 const uint32_t avail = pool_end - pool_next;
                 const uint32_t r = __popcll(m & lanemask_lt());
@@ -1460,7 +1464,7 @@ uint32_t persistent_blocks(const n2v_exec_opts &o, int dev, uint64_t walks)
     if (per_cu > (uint32_t)d.occ) per_cu = d.occ;
     if (per_cu < 1) per_cu = 1;
     uint64_t blocks = (uint64_t)d.cus * per_cu;
-    const uint64_t need = (walks + PBLOCK - 1) / PBLOCK;
+    const uint64_t need = (walks + WAVE - 1) / WAVE;  // small jobs: spread walks thin over more wavefronts
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
     return (uint32_t)blocks;
