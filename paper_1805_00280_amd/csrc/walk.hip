@@ -776,6 +776,26 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
         c += 1;
         wave_lds_sync();
     }
+    // the positions give the sketch's per-segment counts (start hints stay
+    // unknown), so later moves along this pair take the dense path's one-segment
+    // recompute instead of searching again
+    if (E.g.memo && !E.g.wt && st.pos_t != SENT && dv > E.g.d_rule) {
+        const uint32_t nsub = (dv + TX - 1) / TX;
+        const uint32_t G = (nsub + NSUPER - 1) / NSUPER;
+        const uint32_t nsup = (nsub + G - 1) / G;
+        const uint32_t seglen = G * TX;
+        uint32_t *cnt = (uint32_t *)L.b.dl;
+        cnt[l] = 0;
+        wave_lds_sync();
+        for (uint32_t k = l; k < c; k += WAVE) {
+            const uint32_t q = L.a.sp.pos[k];
+            if (q != st.pos_t) atomicAdd(&cnt[q / seglen], 1u);
+        }
+        wave_lds_sync();
+        if ((uint32_t)l < nsup)
+            __builtin_nontemporal_store((uint16_t)(cnt[l] + 1), sketch_row(E, st.v, st.pos_t) + l);
+        wave_lds_sync();
+    }
     int64_t dsum = 0;
     for (uint32_t k = l; k < c; k += WAVE) dsum += special_delta(E, J, st, L.a.sp.pos[k]);
     dsum = (int64_t)wave_sum((uint64_t)dsum);
@@ -970,7 +990,17 @@ __device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx
         if (!E.g.wt) return (uint32_t)hi64(R1, st.vd);
         return weighted_scan_locate(E, J, st, L, 1u, 0u, hi64(R1, E.g.wsum[st.v]));
     }
-    uint32_t j = use_sparse(E, st) ? hub_sparse(E, J, st, L, R1) : hub_dense(E, J, st, L, R1);
+    bool sparse = use_sparse(E, st);
+    if (sparse && E.g.memo && !E.g.wt && st.pos_t != SENT && st.vd > E.g.d_rule) {
+        // a sketch that an earlier move filled makes the dense path cheaper
+        const uint32_t nsub = (st.vd + TX - 1) / TX;
+        const uint32_t G = (nsub + NSUPER - 1) / NSUPER;
+        const uint32_t nsup = (nsub + G - 1) / G;
+        const uint16_t *row = sketch_row(E, st.v, st.pos_t);
+        const uint32_t known = (uint32_t)lane_id() < nsup ? row[lane_id()] : 1u;
+        if (ballot(known == 0) == 0) sparse = false;
+    }
+    uint32_t j = sparse ? hub_sparse(E, J, st, L, R1) : hub_dense(E, J, st, L, R1);
     if (j >= st.vd) {  // cannot happen for a correct rule; keeps every read inside the row
         if (lane_id() == 0) atomicOr(E.g.status, 2u);
         j = st.vd - 1;
@@ -1105,7 +1135,7 @@ __device__ __forceinline__ void ws_to_slot(const WS &st, uint32_t flags, Slot &q
 }
 
 template <class Src, bool WALKS, bool COUNTS>
-__global__ __launch_bounds__(PBLOCK) void k_persistent(Exec E, Src S)
+__global__ __launch_bounds__(PBLOCK, 4) void k_persistent(Exec E, Src S)
 {
     __shared__ HubLds lds[PBLOCK / WAVE];
     __shared__ Slot slots[PBLOCK / WAVE][WAVE];
@@ -1577,7 +1607,7 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
     o->mode = N2V_MODE_AUTO;
     o->t_wave = 64;
     o->t_sparse = 1023;
-    o->sparse_ratio = 16;
+    o->sparse_ratio = 2;
     o->waves_per_cu = 0;
     o->block = 256;
     o->memo = 1;
