@@ -174,29 +174,55 @@ __device__ __forceinline__ void advance(const Exec &E, WS &st, uint32_t j, uint3
     st.s += 1;
 }
 
-// One rejection attempt k; returns whether it accepts and its neighbour index.
-__device__ __forceinline__ bool attempt(const Exec &E, const JobCtx &J, const WS &st, uint32_t k, uint32_t &j_out)
+// Rejection attempt k up to the membership test: the proposal j and, unless
+// the outcome is already forced, the proposal x and the acceptance draw u
+// against A * w (A = A_COM if x is a neighbour of t, else A_out).  Returns
+// 1 (accept), 0 (reject) or 2 (the test is needed).
+struct Att {
+    uint32_t j, x;
+    uint64_t u, w;
+};
+
+__device__ __forceinline__ int attempt_pre(const Exec &E, const JobCtx &J, const WS &st, uint32_t k, Att &a)
 {
     const bool first = st.s == 0;
     const uint64_t E_env = (uint64_t)st.vw * (first ? 1u : amax3(J));
     const R4 r = philox(J.k0, J.k1, J.wbase + st.i, st.s, k, 0u);
     const uint64_t j = hi64(join64(r.x, r.y), st.vd);
-    const uint64_t u = hi64(join64(r.z, r.w), E_env);
-    const uint64_t w = E.g.wt ? E.g.wt[st.vo + j] : 1u;
+    a.j = (uint32_t)j;
+    a.u = hi64(join64(r.z, r.w), E_env);
+    a.w = E.g.wt ? E.g.wt[st.vo + j] : 1u;
     const uint32_t acmin = A_COM < J.A_out ? A_COM : J.A_out;
     const uint32_t acmax = A_COM < J.A_out ? J.A_out : A_COM;
-    bool acc;
-    if (first) acc = u < w;
-    else if (j == st.pos_t) acc = u < J.A_ret * w;
-    else if (u < acmin * w) acc = true;
-    else if (u >= acmax * w) acc = false;
-    else {
-        const uint32_t x = E.g.adj[st.vo + j];
-        const bool com = contains_g(E.g.adj, st.to, st.to + st.td, x);
-        acc = u < (uint64_t)(com ? A_COM : J.A_out) * w;
+    if (first) return a.u < a.w;
+    if (j == st.pos_t) return a.u < J.A_ret * a.w;
+    if (a.u < acmin * a.w) return 1;
+    if (a.u >= acmax * a.w) return 0;
+    a.x = E.g.adj[st.vo + j];
+    return 2;
+}
+
+// One rejection attempt k; returns whether it accepts and its neighbour index.
+__device__ __forceinline__ bool attempt(const Exec &E, const JobCtx &J, const WS &st, uint32_t k, uint32_t &j_out)
+{
+    Att a;
+    const int r = attempt_pre(E, J, st, k, a);
+    j_out = a.j;
+    if (r < 2) return r == 1;
+    const bool com = contains_g(E.g.adj, st.to, st.to + st.td, a.x);
+    return a.u < (uint64_t)(com ? A_COM : J.A_out) * a.w;
+}
+
+// x in the sorted LDS array T[0, n): a branchless lower bound (the bound lies
+// in [p, p + len - 1] throughout), then one compare.
+__device__ __forceinline__ bool lds_contains(const uint32_t *T, uint32_t n, uint32_t x)
+{
+    const uint32_t *q = T;
+    for (uint32_t len = n; len > 1; len -= len >> 1) {
+        const uint32_t half = len >> 1;
+        q += q[half - 1] < x ? half : 0u;
     }
-    j_out = (uint32_t)j;
-    return acc;
+    return n > 0 && *q == x;
 }
 
 // Thread class: attempts in order until one accepts (false after a_cap).
@@ -208,20 +234,39 @@ __device__ bool thread_reject(const Exec &E, const JobCtx &J, const WS &st, uint
 }
 
 // Wave class: lanes take attempts k0 + lane; the lowest accepting one wins.
-__device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, uint32_t &j_out)
+// When some attempt needs "is x a neighbour of t?" and N(t) fits, the wave
+// stages N(t) in LDS once (one coalesced read) and searches it there.
+__device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, HubLds &L, uint32_t &j_out)
 {
     const WS st = uniform_ws(st_in);
     const int l = lane_id();
+    bool staged = false;
     for (uint32_t k0 = 0; k0 < E.g.a_cap; k0 += WAVE) {
         const uint32_t k = k0 + l;
-        uint32_t j = 0;
-        const bool acc = k < E.g.a_cap && attempt(E, J, st, k, j);
+        Att a;
+        a.j = 0;
+        const int r = k < E.g.a_cap ? attempt_pre(E, J, st, k, a) : 0;
+        bool acc = r == 1;
+        if (ballot(r == 2)) {
+            if (!staged && st.td <= (uint32_t)SPCAP) {
+                for (uint32_t i = l; i < st.td; i += WAVE) L.a.sp.pos[i] = E.g.adj[st.to + i];
+                wave_lds_sync();
+                staged = true;
+            }
+            if (r == 2) {
+                const bool com = staged ? lds_contains(L.a.sp.pos, st.td, a.x)
+                                        : contains_g(E.g.adj, st.to, st.to + st.td, a.x);
+                acc = a.u < (uint64_t)(com ? A_COM : J.A_out) * a.w;
+            }
+        }
         const uint64_t m = ballot(acc);
         if (m) {
-            j_out = lane_val(j, first_lane(m));
+            j_out = lane_val(a.j, first_lane(m));
+            wave_lds_sync();
             return true;
         }
     }
+    wave_lds_sync();
     return false;
 }
 
@@ -1242,7 +1287,7 @@ __global__ __launch_bounds__(PBLOCK, 4) void k_persistent(Exec E, Src S)
             for (;;) {
                 uint32_t j = 0, kidx = capped ? E.g.a_cap : 0u;
                 bool icdf = capped || w.vd > E.g.d_rule;
-                if (!icdf && !wave_reject(E, J, w, j)) {
+                if (!icdf && !wave_reject(E, J, w, L, j)) {
                     icdf = true;
                     kidx = E.g.a_cap;
                 }
@@ -1605,7 +1650,7 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
         return;
     }
     o->mode = N2V_MODE_AUTO;
-    o->t_wave = 64;
+    o->t_wave = 256;
     o->t_sparse = 1023;
     o->sparse_ratio = 2;
     o->waves_per_cu = 0;
