@@ -434,6 +434,7 @@ __device__ __forceinline__ void pivot_buckets(const HubLds &L, uint32_t np, cons
 // search inside the bucket, SEARCH_ILP entries per lane at a time.  Returns
 // the number flagged; lb0 receives the lower bound in N(t) of the tile's first
 // entry.  Matches are also counted in R.rc (reverse start hints stay unknown).
+// The tile's entries are left in LDS (xs) as by dense_flags.
 __device__ uint32_t search_flags(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y, uint32_t ylo,
                                  uint32_t yhi, uint32_t np, uint32_t B, HubLds &L, uint32_t j0, uint32_t cnt,
                                  const RevSketch &R, uint32_t &lb0)
@@ -447,6 +448,7 @@ __device__ uint32_t search_flags(const uint32_t *__restrict__ X, const uint32_t 
         for (int k = 0; k < SEARCH_ILP; ++k) {
             const uint32_t i = (h + k) * WAVE + l;
             x[k] = i < cnt ? X[j0 + i] : 0xFFFFFFFFu;
+            L.a.d.xs[i] = x[k];  // the tile, for the caller's answer
         }
         pivot_buckets(L, np, x, p);  // bucket index, np past the last
 #pragma unroll
@@ -573,7 +575,7 @@ __device__ __forceinline__ uint16_t *rev_setup(const Exec &E, const WS &st, uint
 // (from the pair sketch when it is known, else by a merge-intersection pass
 // that also fills the sketch and its reverse), then one segment is recomputed
 // to find the entry whose prefix sum first exceeds r.
-__device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, uint64_t R1)
+__device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubLds &L, uint64_t R1, uint32_t &xj)
 {
     const int l = lane_id();
     const uint32_t *__restrict__ X = E.g.adj + st.vo;
@@ -703,6 +705,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             dense_flags(X, Y, td, L, j0, cnt, ypos, none);
         }
         const uint32_t j = dense_chunk_locate(W, J, pos_t, L, j0, cnt, base, r);
+        if (j != SENT) xj = L.a.d.xs[j - j0];  // the chosen neighbour, still in the tile
         wave_lds_sync();
         if (j != SENT) return j;
     }
@@ -1026,8 +1029,12 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
 }
 
 // Inverse CDF of one move by a wavefront (state uniform across lanes).
-__device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &st_in, uint32_t kidx, HubLds &L)
+// xj receives the chosen neighbour when the evaluation already holds it, else
+// SENT.
+__device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &st_in, uint32_t kidx,
+                                                     HubLds &L, uint32_t &xj)
 {
+    xj = SENT;
     const WS st = uniform_ws(st_in);
     const R4 rr = philox(J.k0, J.k1, J.wbase + st.i, st.s, kidx, 0u);
     const uint64_t R1 = join64(rr.x, rr.y);
@@ -1045,10 +1052,11 @@ __device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx
         const uint32_t known = (uint32_t)lane_id() < nsup ? row[lane_id()] : 1u;
         if (ballot(known == 0) == 0) sparse = false;
     }
-    uint32_t j = sparse ? hub_sparse(E, J, st, L, R1) : hub_dense(E, J, st, L, R1);
+    uint32_t j = sparse ? hub_sparse(E, J, st, L, R1) : hub_dense(E, J, st, L, R1, xj);
     if (j >= st.vd) {  // cannot happen for a correct rule; keeps every read inside the row
         if (lane_id() == 0) atomicOr(E.g.status, 2u);
         j = st.vd - 1;
+        xj = SENT;
     }
     return j;
 }
@@ -1291,9 +1299,17 @@ __global__ __launch_bounds__(PBLOCK, 4) void k_persistent(Exec E, Src S)
                     icdf = true;
                     kidx = E.g.a_cap;
                 }
-                if (icdf) j = wave_inverse_cdf(E, J, w, kidx, L);
+                uint32_t xj = SENT;
+                if (icdf) j = wave_inverse_cdf(E, J, w, kidx, L, xj);
                 uint32_t x, rev;
-                resolve(E, w, j, x, rev);
+                if (xj != SENT && !(w.s > 0 && j == w.pos_t)) {
+                    // the neighbour is known: its record and the reverse
+                    // position load together
+                    x = xj;
+                    rev = E.g.erec[w.vo + j].y;
+                } else {
+                    resolve(E, w, j, x, rev);
+                }
                 x = uni(x);
                 rev = uni(rev);
                 if (l == 0) emit<WALKS, COUNTS>(J, w.i, w.s + 1, x, csum);
@@ -1481,7 +1497,8 @@ __global__ __launch_bounds__(HBLOCK, 5) void k_plain_hub(Exec E, OneJob S, uint3
         const uint32_t kidx = (item & 0x80000000u) ? E.g.a_cap : 0u;
         WS st;
         plain_load(E, state[i], i, s, st);
-        const uint32_t j = wave_inverse_cdf(E, S.c, st, kidx, L);
+        uint32_t xj;
+        const uint32_t j = wave_inverse_cdf(E, S.c, st, kidx, L, xj);
         plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, true);
     }
     if (COUNTS) {
@@ -1657,7 +1674,7 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
     o->block = 256;
     o->memo = 1;
     o->t_wg = 8192;
-    o->search_ratio = 4;
+    o->search_ratio = 8;
 }
 
 extern "C" int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_t L, const n2v_exec_opts *opts,
