@@ -157,7 +157,7 @@ typedef struct {
     uint32_t memo;       /* 1: use the graph's pair sketches when attached (default 1) */
     uint32_t t_wg;       /* plain: dense hub moves at degree > max(t_wg, d_rule) are evaluated by
                             a whole workgroup (its wavefronts split the merge), the others by one
-                            wavefront each (default 8192) */
+                            wavefront each (default 65536) */
     uint32_t search_ratio; /* dense hub moves look N(v)'s entries up in N(t) (pivots in LDS, then
                             a search in one bucket) instead of streaming N(t) when the part of
                             N(t) to stream is more than search_ratio times longer (default 8;

@@ -890,12 +890,14 @@ __device__ __forceinline__ bool use_sparse(const Exec &E, const WS &st)
 
 // ------------------------------------------------ workgroup per hub move
 constexpr int HBLOCK = 256;  // plain hub kernel workgroup
+constexpr int HUB_CLAIM = 8; // plain hub moves a wavefront claims per atomic
 constexpr int HWAVES = HBLOCK / WAVE;
 
 // LDS a workgroup shares while it evaluates one move together.
 struct BlkLds {
     uint64_t csum[NSUPER];   // per-segment sums of pi
     uint32_t ystart[NSUPER]; // per-segment start in N(t) (SENT: search)
+    uint32_t ycap[NSUPER];   // an index at or above each segment's start
     uint32_t rc[NSUPER];     // reverse sketch counts
     uint32_t rh[NSUPER];     // reverse sketch hints
     uint64_t part[HWAVES];   // tile sums of one locate round
@@ -928,12 +930,16 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
     // even while another group is filling the same row
     if (wv == 0) {
         bool warm = false;
-        uint32_t known = 1, ys = SENT;
+        uint32_t known = 1, ys = SENT, yc = td;
         if (row) {
             if ((uint32_t)l < nsup) {
                 known = row[l];
                 const uint32_t h = row[MEMO_SEGS + l];
-                if (h) ys = (h - 1) << hs;
+                if (h) {
+                    ys = (h - 1) << hs;
+                    const uint64_t up = (uint64_t)h << hs;
+                    yc = up < td ? (uint32_t)up : td;
+                }
             }
             warm = ballot(known == 0) == 0;
         }
@@ -942,6 +948,7 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
             B.csum[l] = seg_pi(J, pos_t, a, dv - a < seglen ? dv - a : seglen, known - 1);
         }
         B.ystart[l] = ys;
+        B.ycap[l] = yc;
         B.rc[l] = 0;
         B.rh[l] = 0;
         if (l == 0) B.warm = warm;
@@ -953,17 +960,26 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
         if (row) rrow = rev_setup(E, st, B.rc, B.rh, R);
         else R.rseg = 0;
         const uint32_t sp0 = wv * nsup / HWAVES, sp1 = (wv + 1) * nsup / HWAVES;
+        const bool srch = (uint64_t)td > (uint64_t)E.search_ratio * dv;
         if (sp0 < sp1) {
-            uint32_t ypos = td ? wave_lower_bound(Y, td, X[sp0 * seglen]) : 0;
+            const uint32_t Bp = srch ? load_pivots(Y, 0, td, L, NPIV) : 0;
+            uint32_t ypos = !srch && td ? wave_lower_bound(Y, td, X[sp0 * seglen]) : 0;
             for (uint32_t sp = sp0; sp < sp1; ++sp) {
                 uint64_t sum = 0;
                 uint32_t csp = 0;
-                const uint32_t ys = ypos;
+                uint32_t ys = ypos;
                 const uint32_t sub_end = nsub < (sp + 1) * G ? nsub : (sp + 1) * G;
                 for (uint32_t sub = sp * G; sub < sub_end; ++sub) {
                     const uint32_t j0 = sub * TX;
                     const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
-                    const uint32_t c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
+                    uint32_t c;
+                    if (srch) {
+                        uint32_t lb0;
+                        c = search_flags(X, Y, 0, td, NPIV, Bp, L, j0, cnt, R, lb0);
+                        if (sub == sp * G) ys = lb0;
+                    } else {
+                        c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
+                    }
                     sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, c);
                     csp += c;
                     wave_lds_sync();
@@ -971,6 +987,7 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
                 if (l == 0) {
                     B.csum[sp] = sum;
                     B.ystart[sp] = ys;
+                    B.ycap[sp] = ys;
                     if (row) {
                         __builtin_nontemporal_store((uint16_t)(csp + 1), row + sp);
                         __builtin_nontemporal_store((uint16_t)((ys >> hs) + 1), row + MEMO_SEGS + sp);
@@ -993,9 +1010,17 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
     const uint64_t m = ballot((uint32_t)l < nsup && inc > r);
     const uint32_t spx = m ? (uint32_t)first_lane(m) : nsup - 1;
     uint64_t base = lane_val64(inc - c, (int)spx);
-    const uint32_t yseg = B.ystart[spx];
+    // the matches of segment spx lie in N(t)[ylo, yhi)
+    uint32_t ylo = B.ystart[spx];
+    if (ylo == SENT) ylo = td ? wave_lower_bound(Y, td, X[spx * seglen]) : 0;
+    if (ylo > td) ylo = td;
+    uint32_t yhi = spx + 1 < nsup ? B.ycap[spx + 1] : td;
+    if (yhi < ylo) yhi = ylo;
+    const uint32_t xlen = dv - spx * seglen < seglen ? dv - spx * seglen : seglen;
+    const bool lsrch = (uint64_t)(yhi - ylo) > (uint64_t)E.search_ratio * xlen;
     const RevSketch none = {0, 0, nullptr, nullptr};
     const uint32_t sub_end = nsub < (spx + 1) * G ? nsub : (spx + 1) * G;
+    const uint32_t Bl = lsrch && spx * G + wv < sub_end ? load_pivots(Y, ylo, yhi, L, NPIV) : 0;
     for (uint32_t b = spx * G; b < sub_end; b += HWAVES) {
         const uint32_t sub = b + wv;
         const bool has = sub < sub_end;
@@ -1003,10 +1028,15 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
         const uint32_t cnt = has ? (dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX) : 0;
         uint64_t tsum = 0;
         if (has) {
-            uint32_t ypos = sub == spx * G ? yseg : SENT;
-            if (ypos == SENT) ypos = td ? wave_lower_bound(Y, td, X[j0]) : 0;
-            if (ypos > td) ypos = td;
-            const uint32_t cc = dense_flags(X, Y, td, L, j0, cnt, ypos, none);
+            uint32_t cc;
+            if (lsrch) {
+                uint32_t lb0;
+                cc = search_flags(X, Y, ylo, yhi, NPIV, Bl, L, j0, cnt, none, lb0);
+            } else {
+                uint32_t ypos = ylo;
+                if (sub != spx * G) ypos = ylo + wave_lower_bound(Y + ylo, yhi - ylo, X[j0]);
+                cc = dense_flags(X, Y, td, L, j0, cnt, ypos, none);
+            }
             tsum = W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, cc);
         }
         if (l == 0) B.part[wv] = tsum;
@@ -1486,20 +1516,25 @@ __global__ __launch_bounds__(HBLOCK, 5) void k_plain_hub(Exec E, OneJob S, uint3
             plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, true);
         }
     }
+    // wavefront moves, HUB_CLAIM per atomic (one counter serves the whole
+    // superstep, so single-move claims would serialise on it)
     const uint32_t n = *hubn;
     for (;;) {
-        uint32_t q = 0;
-        if (lane_id() == 0) q = atomicAdd(hubd, 1u);
-        q = uni(q);
-        if (q >= n) break;
-        const uint32_t item = uni(hubq[q]);
-        const uint32_t i = item & 0x7FFFFFFFu;
-        const uint32_t kidx = (item & 0x80000000u) ? E.g.a_cap : 0u;
-        WS st;
-        plain_load(E, state[i], i, s, st);
-        uint32_t xj;
-        const uint32_t j = wave_inverse_cdf(E, S.c, st, kidx, L, xj);
-        plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, true);
+        uint32_t q0 = 0;
+        if (lane_id() == 0) q0 = atomicAdd(hubd, (uint32_t)HUB_CLAIM);
+        q0 = uni(q0);
+        if (q0 >= n) break;
+        const uint32_t q1 = n - q0 < (uint32_t)HUB_CLAIM ? n : q0 + HUB_CLAIM;
+        for (uint32_t q = q0; q < q1; ++q) {
+            const uint32_t item = uni(hubq[q]);
+            const uint32_t i = item & 0x7FFFFFFFu;
+            const uint32_t kidx = (item & 0x80000000u) ? E.g.a_cap : 0u;
+            WS st;
+            plain_load(E, state[i], i, s, st);
+            uint32_t xj;
+            const uint32_t j = wave_inverse_cdf(E, S.c, st, kidx, L, xj);
+            plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, true);
+        }
     }
     if (COUNTS) {
         csum = wave_sum(csum);
@@ -1673,7 +1708,7 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
     o->waves_per_cu = 0;
     o->block = 256;
     o->memo = 1;
-    o->t_wg = 8192;
+    o->t_wg = 65536;
     o->search_ratio = 8;
 }
 

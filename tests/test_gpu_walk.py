@@ -318,9 +318,9 @@ def check_sketch_rows(og, memo, d_rule, limit=6000, seed=1):
     return len(touched)
 
 
-@pytest.mark.parametrize("mode,t_wg,search", [(P.MODE_PERSISTENT, 8192, 2), (P.MODE_PLAIN, 8192, 2),
-                                               (P.MODE_PLAIN, 0, 2), (P.MODE_PERSISTENT, 8192, 0),
-                                               (P.MODE_PERSISTENT, 8192, 0xFFFFFFFF)])
+@pytest.mark.parametrize("mode,t_wg,search", [(P.MODE_PERSISTENT, 65536, 2), (P.MODE_PLAIN, 65536, 2),
+                                               (P.MODE_PLAIN, 0, 2), (P.MODE_PERSISTENT, 65536, 0),
+                                               (P.MODE_PERSISTENT, 65536, 0xFFFFFFFF)])
 def test_pair_sketch_contents(mode, t_wg, search):
     # the sketches written during a call (by forward merges and by the reverse pairs they also
     # count) hold exact per-segment common-neighbour counts
