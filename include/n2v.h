@@ -52,7 +52,7 @@ extern "C" {
 #endif
 
 #define N2V_SENT 0xFFFFFFFFu
-#define N2V_ABI_VERSION 3
+#define N2V_ABI_VERSION 4
 
 enum {
     N2V_OK = 0,
@@ -205,6 +205,19 @@ int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, u
  * attaches caller device memory (NULL detaches). */
 int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes);
 int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes);
+
+/* Sketches for part of the hub rows, when all of them do not fit: only moves
+ * at vertices of degree >= min_degree (> d_rule) keep sketches; the other hub
+ * moves take the full pass every time.  n2v_graph_memo_plan returns the
+ * smallest such threshold (d_rule + 1, else a power of two) whose rows fit in
+ * `budget` bytes, and those rows' bytes (*min_degree = 0xFFFFFFFF and *bytes =
+ * 0 when none fit; weighted graphs: N2V_EINVAL).  It synchronises the device.
+ * n2v_graph_set_memo_min attaches `bytes` of device memory (256-byte aligned)
+ * for rows of degree >= min_degree; it re-indexes the rows on the default
+ * stream and synchronises, so no walk on this graph may be in flight.
+ * N2V_ENOMEM if `bytes` is too small.  NULL detaches. */
+int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *min_degree, size_t *bytes);
+int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uint32_t min_degree);
 
 /* Synchronises the stream and returns N2V_EINVAL if any walk since the last
  * check had a start id >= n, N2V_EDEVICE if a kernel detected an internal

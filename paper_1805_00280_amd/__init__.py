@@ -29,6 +29,7 @@ EXPORTS = [
     "n2v_rmat_workspace", "n2v_rmat_generate",
     "n2v_graph_opts_default", "n2v_graph_workspace", "n2v_graph_create", "n2v_graph_destroy",
     "n2v_graph_info", "n2v_graph_check", "n2v_graph_memo_bytes", "n2v_graph_set_memo",
+    "n2v_graph_memo_plan", "n2v_graph_set_memo_min",
     "n2v_exec_opts_default", "n2v_walk", "n2v_walk_workspace", "n2v_walk_ex",
     "n2v_autotune_workspace", "n2v_autotune",
     "n2v_server_opts_default", "n2v_server_create", "n2v_server_destroy", "n2v_submit", "n2v_poll",
@@ -76,7 +77,7 @@ class Result(C.Structure):
                 ("start_ns", C.c_uint64), ("done_ns", C.c_uint64)]
 
 
-ABI_VERSION = 3  # layout of the option structs below
+ABI_VERSION = 4  # layout of the option structs below
 _lib = None
 
 
@@ -104,6 +105,8 @@ def lib():
         "n2v_graph_check": ([vp, vp], i32),
         "n2v_graph_memo_bytes": ([vp, P(sz)], i32),
         "n2v_graph_set_memo": ([vp, vp, sz], i32),
+        "n2v_graph_memo_plan": ([vp, sz, P(u32), P(sz)], i32),
+        "n2v_graph_set_memo_min": ([vp, vp, sz, u32], i32),
         "n2v_exec_opts_default": ([vp, P(ExecOpts)], None),
         "n2v_walk": ([vp, vp, u32, u32, f32, f32, u64, vp, vp], i32),
         "n2v_walk_workspace": ([vp, u32, u32, P(ExecOpts), P(sz)], i32),
@@ -186,6 +189,8 @@ class Graph:
         self._h = h
         self.d_rule, self.a_cap = d_rule, a_cap
         self.weighted = wt is not None
+        self.memo = None
+        self.memo_min_degree = None
         del torch
 
     @staticmethod
@@ -243,14 +248,26 @@ class Graph:
         check(lib().n2v_graph_info(self._h, C.byref(n), C.byref(m), C.byref(d), C.byref(a), C.byref(w)))
         return {"n": n.value, "m": m.value, "d_rule": d.value, "a_cap": a.value, "weighted": bool(w.value)}
 
-    def attach_memo(self):
-        """Allocates and attaches the pair-sketch memory (unweighted graphs); returns its bytes."""
-        b = C.c_size_t()
-        check(lib().n2v_graph_memo_bytes(self._h, C.byref(b)), "n2v_graph_memo_bytes")
+    def attach_memo(self, budget=None):
+        """Allocates and attaches pair-sketch memory (unweighted graphs); returns its bytes.  With a
+        byte budget, only rows of the highest-degree vertices that fit keep sketches (0 if none)."""
+        if budget is None:
+            b = C.c_size_t()
+            check(lib().n2v_graph_memo_bytes(self._h, C.byref(b)), "n2v_graph_memo_bytes")
+            if b.value == 0:
+                return 0
+            self.memo = _alloc(b.value, self.device)
+            check(lib().n2v_graph_set_memo(self._h, _ptr(self.memo), self.memo.numel()), "n2v_graph_set_memo")
+            self.memo_min_degree = self.d_rule + 1
+            return b.value
+        dmin, b = C.c_uint32(), C.c_size_t()
+        check(lib().n2v_graph_memo_plan(self._h, int(budget), C.byref(dmin), C.byref(b)), "n2v_graph_memo_plan")
         if b.value == 0:
             return 0
         self.memo = _alloc(b.value, self.device)
-        check(lib().n2v_graph_set_memo(self._h, _ptr(self.memo), self.memo.numel()), "n2v_graph_set_memo")
+        check(lib().n2v_graph_set_memo_min(self._h, _ptr(self.memo), self.memo.numel(), dmin.value),
+              "n2v_graph_set_memo_min")
+        self.memo_min_degree = dmin.value
         return b.value
 
     def detach_memo(self):

@@ -50,13 +50,14 @@ struct DevGraph {
     const uint32_t *adj;   // m, rows strictly ascending
     const uint16_t *wt;    // m, or null for an unweighted graph
     const uint64_t *wsum;  // n: row weight sums (weighted graphs only)
-    const uint64_t *hbase; // n+1: first memo entry of each row of degree > d_rule
+    const uint64_t *hbase; // n+1: first sketch row of each vertex of degree >= memo_min
     uint16_t *memo;        // pair sketches (hbase[n] rows of MEMO_ROW u16) or null
     uint32_t *status;      // device flags: bit 0 = a start id was out of range
     uint32_t *cursors;     // CURSOR_SLOTS walk counters, one per concurrent call
     uint32_t n;
     uint64_t m;
     uint32_t d_rule;
+    uint32_t memo_min;     // vertices of at least this degree (> d_rule) have sketch rows
     uint32_t a_cap;
 };
 
@@ -223,6 +224,8 @@ struct n2v_graph {
     bool has_tuned;
     n2v_exec_opts tuned;
     uint64_t hub_entries;   // entries in rows of degree > d_rule
+    uint64_t memo_entries;  // entries in rows of degree >= dg.memo_min (sketch rows)
+    void *scan;             // scan scratch of the graph's workspace
     uint32_t next_cursor;   // round-robin counter slot
     size_t memo_bytes;      // attached sketch memory (0: none)
 };

@@ -3,6 +3,8 @@
 // row weight sums and maxima).
 #include <stdlib.h>
 
+#include <algorithm>
+
 #include "prims.hpp"
 
 namespace n2v {
@@ -78,14 +80,31 @@ __global__ __launch_bounds__(256) void k_derive(const uint64_t *__restrict__ off
     if (flags) atomicOr(bad, flags);
 }
 
-// hbase[v] = deg(v) when deg(v) > d_rule, else 0 (scanned afterwards).
-__global__ void k_hub_len(const uint64_t *__restrict__ off, uint32_t n, uint32_t d_rule, uint64_t *__restrict__ hb)
+// hbase[v] = deg(v) when deg(v) >= dmin, else 0 (scanned afterwards).
+__global__ void k_hub_len(const uint64_t *__restrict__ off, uint32_t n, uint64_t dmin, uint64_t *__restrict__ hb)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride) {
         const uint64_t d = v < n ? off[v + 1] - off[v] : 0;
-        hb[v] = d > d_rule ? d : 0;
+        hb[v] = d >= dmin ? d : 0;
     }
+}
+
+// Entries in rows of degree in [2^k, 2^(k+1)), k = 0..63, over rows of degree
+// >= dmin (a per-block histogram, then one atomic per bin).
+__global__ __launch_bounds__(256) void k_deg_hist(const uint64_t *__restrict__ off, uint32_t n, uint64_t dmin,
+                                                  unsigned long long *__restrict__ hist)
+{
+    __shared__ unsigned long long h[64];
+    if (threadIdx.x < 64) h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint64_t d = off[v + 1] - off[v];
+        if (d >= dmin && d > 0) atomicAdd(&h[63 - __clzll((long long)d)], (unsigned long long)d);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ void k_zero_u32(uint32_t *p, uint32_t n)
@@ -188,7 +207,8 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
         N2V_HIP(hipStreamSynchronize(st));
         if (bad) return set_error(N2V_EGRAPH, "n2v_graph_create: CSR is not symmetric (flags 0x%x)", bad);
     }
-    hipLaunchKernelGGL(k_hub_len, dim3(grid_for_waves(n)), dim3(256), 0, st, off, n, o.d_rule, L.hbase);
+    const uint64_t memo_min = (uint64_t)o.d_rule + 1;
+    hipLaunchKernelGGL(k_hub_len, dim3(grid_for_waves(n)), dim3(256), 0, st, off, n, memo_min, L.hbase);
     N2V_HIP(hipGetLastError());
     int rc = exclusive_scan_u64(L.hbase, (uint64_t)n + 1, L.scan, st);
     if (rc) return rc;
@@ -200,6 +220,8 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
     g->dg.hbase = L.hbase;
     g->dg.memo = nullptr;
     g->hub_entries = hub_entries;
+    g->memo_entries = hub_entries;
+    g->scan = L.scan;
     g->memo_bytes = 0;
     g->dg.vrec = L.vrec;
     g->dg.erec = L.erec;
@@ -212,6 +234,7 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
     g->dg.n = n;
     g->dg.m = m;
     g->dg.d_rule = o.d_rule;
+    g->dg.memo_min = memo_min > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)memo_min;
     g->dg.a_cap = o.a_cap;
     g->off = off;
     g->weighted = wt != nullptr;
@@ -247,22 +270,85 @@ extern "C" int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes)
     return N2V_OK;
 }
 
-extern "C" int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes)
+extern "C" int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *min_degree, size_t *bytes)
 {
-    if (!g) return set_error(N2V_EINVAL, "n2v_graph_set_memo: null graph");
+    if (!g || !min_degree || !bytes) return set_error(N2V_EINVAL, "n2v_graph_memo_plan: null argument");
+    if (g->weighted) return set_error(N2V_EINVAL, "n2v_graph_memo_plan: weighted graphs keep no pair sketches");
+    const size_t row = MEMO_ROW * sizeof(uint16_t);
+    const uint64_t dmin = (uint64_t)g->dg.d_rule + 1;
+    if (g->hub_entries * row <= budget) {
+        *min_degree = (uint32_t)std::min<uint64_t>(dmin, 0xFFFFFFFFull);
+        *bytes = g->hub_entries * row;
+        return N2V_OK;
+    }
+    unsigned long long *hist = nullptr;
+    N2V_HIP(hipMalloc(&hist, 64 * sizeof(unsigned long long)));
+    unsigned long long h[64];
+    int rc = N2V_OK;
+    if (hipMemset(hist, 0, sizeof(h)) != hipSuccess) rc = hip_fail(hipGetLastError(), "hipMemset");
+    if (!rc) {
+        hipLaunchKernelGGL(k_deg_hist, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin, hist);
+        if (hipMemcpy(h, hist, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = hip_fail(hipGetLastError(), "hipMemcpy");
+    }
+    (void)hipFree(hist);
+    if (rc) return rc;
+    // thresholds: powers of two above d_rule; entries of rows of degree >= 2^k
+    for (int k = 0; k < 64; ++k) {
+        const uint64_t t = 1ull << k;
+        if (t <= dmin) continue;
+        uint64_t e = 0;
+        for (int b = k; b < 64; ++b) e += h[b];
+        if (e * row <= budget) {
+            *min_degree = (uint32_t)std::min<uint64_t>(t, 0xFFFFFFFFull);
+            *bytes = e * row;
+            return N2V_OK;
+        }
+    }
+    *min_degree = 0xFFFFFFFFu;
+    *bytes = 0;
+    return N2V_OK;
+}
+
+extern "C" int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uint32_t min_degree)
+{
+    if (!g) return set_error(N2V_EINVAL, "n2v_graph_set_memo_min: null graph");
     if (!mem) {
         g->dg.memo = nullptr;
         g->memo_bytes = 0;
         return N2V_OK;
     }
-    size_t need = 0;
-    n2v_graph_memo_bytes(g, &need);
-    if (need == 0) return set_error(N2V_EINVAL, "n2v_graph_set_memo: weighted graphs keep no pair sketches");
-    if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
+    if (g->weighted) return set_error(N2V_EINVAL, "n2v_graph_set_memo: weighted graphs keep no pair sketches");
     if (((uintptr_t)mem & 255) != 0) return set_error(N2V_EINVAL, "n2v_graph_set_memo: memory not 256-byte aligned");
+    const uint64_t dmin = std::max<uint64_t>(min_degree, (uint64_t)g->dg.d_rule + 1);
+    if (dmin != g->dg.memo_min) {  // re-index the sketch rows for the new threshold
+        hipLaunchKernelGGL(k_hub_len, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin,
+                           (uint64_t *)g->dg.hbase);
+        N2V_HIP(hipGetLastError());
+        int rc = exclusive_scan_u64((uint64_t *)g->dg.hbase, (uint64_t)g->dg.n + 1, g->scan, 0);
+        if (rc) return rc;
+        uint64_t e = 0;
+        N2V_HIP(hipMemcpy(&e, g->dg.hbase + g->dg.n, sizeof(uint64_t), hipMemcpyDeviceToHost));
+        g->memo_entries = e;
+        g->dg.memo_min = (uint32_t)std::min<uint64_t>(dmin, 0xFFFFFFFFull);
+    }
+    const size_t need = (size_t)g->memo_entries * MEMO_ROW * sizeof(uint16_t);
+    if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
     g->dg.memo = (uint16_t *)mem;
     g->memo_bytes = bytes;
     return N2V_OK;
+}
+
+extern "C" int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes)
+{
+    if (!g) return set_error(N2V_EINVAL, "n2v_graph_set_memo: null graph");
+    if (!mem) return n2v_graph_set_memo_min(g, nullptr, 0, 0);
+    size_t need = 0;
+    n2v_graph_memo_bytes(g, &need);
+    if (need == 0)
+        return set_error(N2V_EINVAL, "n2v_graph_set_memo: no pair sketches (weighted graph, or no row above d_rule)");
+    if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
+    return n2v_graph_set_memo_min(g, mem, bytes, g->dg.d_rule + 1 > g->dg.d_rule ? g->dg.d_rule + 1 : g->dg.d_rule);
 }
 
 extern "C" int n2v_graph_check(const n2v_graph *g, void *stream)

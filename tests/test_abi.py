@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.n2v_abi_version() == 3
+    assert lib.n2v_abi_version() == 4
 
 
 def test_defaults(lib):
@@ -76,3 +76,10 @@ def test_null_arguments_rejected_without_device_work(lib):
     assert lib.n2v_graph_destroy(None) == 0
     assert lib.n2v_server_destroy(None) == 0
     assert lib.n2v_poll(None, 1, None) == -1
+
+
+def test_memo_calls_reject_null_arguments(lib):
+    dmin, b = C.c_uint32(), C.c_size_t()
+    assert lib.n2v_graph_memo_plan(None, 0, C.byref(dmin), C.byref(b)) == -1
+    assert lib.n2v_graph_set_memo_min(None, None, 0, 0) == -1
+    assert lib.n2v_graph_memo_bytes(None, C.byref(b)) == -1

@@ -150,7 +150,7 @@ def test_workgroup_hub_class(weighted, memo):
         assert first_mismatch(got, want) is None, (t_wg, search, first_mismatch(got, want))
     if memo and not weighted:
         torch.cuda.synchronize()
-        n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128), 100)
+        n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128), 101)
         assert n > 100
         g.detach_memo()
 
@@ -277,13 +277,13 @@ def hint_shift(d):
     return max(0, int(d).bit_length() - 15)
 
 
-def check_sketch_rows(og, memo, d_rule, limit=6000, seed=1):
+def check_sketch_rows(og, memo, min_deg, limit=6000, seed=1):
     """Every written pair-sketch row (v, index of t in N(v)) holds, per segment of N(v), one plus the
     number of its entries that are neighbours of t, and start hints into N(t) at or below the lower
     bound of the segment's first entry and not below the end of the previous segment's matches;
     unwritten rows and entries are zero."""
     deg = og.degree()
-    hub = deg > d_rule
+    hub = deg >= min_deg
     hb = np.zeros(og.n + 1, dtype=np.int64)
     hb[1:] = np.cumsum(np.where(hub, deg, 0))
     rows = memo
@@ -335,9 +335,44 @@ def test_pair_sketch_contents(mode, t_wg, search):
     got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=100000, t_wg=t_wg, search_ratio=search)
     torch.cuda.synchronize()
     memo = g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128)
-    n = check_sketch_rows(og, memo, 40)
+    n = check_sketch_rows(og, memo, 41)
     say(f"[walk] sketches mode={mode}: {n} rows written")
     assert n > 1000
     want = oracle_walk(og, starts, 20, 0.25, 4.0, 8, d_rule=40)
     assert first_mismatch(got, want) is None
     g.detach_memo()
+
+
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+def test_pair_sketches_above_degree_threshold(mode):
+    # with a memory budget below the full size, only rows of the highest-degree vertices keep
+    # sketches; results are unchanged, and re-attaching the full size re-indexes the rows
+    import torch
+    torch_cuda()
+    og = oracle_rmat(14, 16, *SKEW, 14, False)
+    g = gpu_graph_from_oracle(og, d_rule=40)
+    full = g.attach_memo()
+    g.detach_memo()
+    deg = og.degree()
+    got_bytes = g.attach_memo(budget=full // 3)
+    T = g.memo_min_degree
+    assert 41 < T < 2 ** 20 and got_bytes == int(deg[deg >= T].sum()) * 256 <= full // 3
+    # the smaller power of two would not have fit
+    assert T // 2 <= 41 or int(deg[deg >= T // 2].sum()) * 256 > full // 3
+    hubs = np.argsort(deg)[-256:].astype(np.uint32)
+    starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
+    want = oracle_walk(og, starts, 20, 0.25, 4.0, 8, d_rule=40)
+    say(f"[walk] sketches above degree {T} mode={mode}")
+    got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=4)
+    assert first_mismatch(got, want) is None
+    torch.cuda.synchronize()
+    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128), T)
+    assert n > 100
+    g.detach_memo()
+    assert g.attach_memo() == full
+    got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=4)
+    assert first_mismatch(got, want) is None
+    torch.cuda.synchronize()
+    assert check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128), 41) > 100
+    g.detach_memo()
+    assert g.attach_memo(budget=0) == 0
