@@ -52,7 +52,7 @@ extern "C" {
 #endif
 
 #define N2V_SENT 0xFFFFFFFFu
-#define N2V_ABI_VERSION 4
+#define N2V_ABI_VERSION 5
 
 enum {
     N2V_OK = 0,
@@ -192,16 +192,16 @@ int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, u
 
 /* Pair sketches (unweighted graphs): memory in which walk calls memoise,
  * for every traversed move (t -> v) at a vertex v of degree > d_rule, the
- * exact number of members of N(t) in each of 64 equal segments of N(v) (as
- * count + 1; 0 = unknown), and for each segment a hint where its merge may
- * start in N(t).  A later move along the same pair then recomputes one
- * segment instead of the whole intersection.  A merge for (t -> v) also
+ * exact number of members of N(t) in each of 64 equal segments of N(v) and in
+ * each segment's first half (as count + 1; 0 = unknown), and for each segment
+ * a hint where its merge may start in N(t).  A later move along the same pair
+ * then recomputes half a segment instead of the whole intersection.  A merge for (t -> v) also
  * fills the sketch of (v -> t) when t has degree > d_rule.  Results never
  * depend on the sketches: unknown entries are recomputed, and every known
  * entry is exact (hints never point past the segment's first candidate).
  * Each walk call clears them first, so no call reuses another call's work;
  * concurrent calls on one graph share them.  n2v_graph_memo_bytes returns the
- * size (hub entries x 256 bytes; 0 for weighted graphs); n2v_graph_set_memo
+ * size (hub entries x 384 bytes; 0 for weighted graphs); n2v_graph_set_memo
  * attaches caller device memory (NULL detaches). */
 int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes);
 int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes);

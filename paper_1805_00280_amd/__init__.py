@@ -77,7 +77,7 @@ class Result(C.Structure):
                 ("start_ns", C.c_uint64), ("done_ns", C.c_uint64)]
 
 
-ABI_VERSION = 4  # layout of the option structs below
+ABI_VERSION = 5  # layout of the option structs and sketch rows
 _lib = None
 
 

@@ -17,9 +17,10 @@ constexpr int WAVE = 64;
 // Segments per pair sketch: a sketch of the move (t -> v) at a hub v holds,
 // for each of up to MEMO_SEGS segments of N(v), one plus the number of
 // members of N(t) in that segment (0 = not known yet), then, per segment, a
-// start hint into N(t) (MEMO_ROW u16 per sketch).
+// start hint into N(t), then one plus the count in the segment's first half
+// (MEMO_ROW u16 per sketch).
 constexpr int MEMO_SEGS = 64;
-constexpr int MEMO_ROW = 2 * MEMO_SEGS;
+constexpr int MEMO_ROW = 3 * MEMO_SEGS;
 // Walk counters a graph hands out round-robin to persistent launches: up to
 // this many launches on one graph may overlap.
 constexpr int CURSOR_SLOTS = 64;

@@ -68,6 +68,7 @@ struct HubLds {
             uint8_t flag[TX];
             uint32_t rc[NSUPER];  // reverse sketch: members of N(v) per segment of N(t)
             uint32_t rh[NSUPER];  // reverse sketch: encoded start hints
+            uint32_t r1[NSUPER];  // reverse sketch: members in each segment's first half
         } d;
         struct {
             uint32_t pos[SPCAP];
@@ -290,6 +291,7 @@ struct RevSketch {
     uint32_t shift;  // hint_shift(deg v)
     uint32_t *rc;    // LDS counts
     uint32_t *rh;    // LDS encoded hints
+    uint32_t *r1;    // LDS counts in each segment's first half
 };
 
 // Flags the tile entries equal to a block of NB x 64 entries of N(t) loaded
@@ -333,7 +335,10 @@ __device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB
             if (hit) L.a.d.flag[pos[k]] = 1;
             if (R.rseg && in && (hit || (idx & (TX - 1)) == 0)) {
                 const uint32_t q = idx / R.rseg;
-                if (hit) atomicAdd(&R.rc[q], 1u);
+                if (hit) {
+                    atomicAdd(&R.rc[q], 1u);
+                    if (idx - q * R.rseg < R.rseg / 2) atomicAdd(&R.r1[q], 1u);
+                }
                 if (idx == q * R.rseg) R.rh[q] = ((j0 + pos[k]) >> R.shift) + 1;
             }
         }
@@ -345,7 +350,8 @@ __device__ __forceinline__ uint32_t flag_block(HubLds &L, const uint32_t (&y)[NB
 // streaming N(t) from ypos (advanced past every value <= the tile's last
 // entry).  The tile and a first, small block of N(t) are loaded together
 // (most windows are short); a block consumed entirely is followed by
-// full-size blocks.  Returns the number of flagged entries.
+// full-size blocks.  Returns the number of flagged entries, plus 2^16 times
+// the number among the tile's first 256 entries.
 __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y, uint32_t td,
                                 HubLds &L, uint32_t j0, uint32_t cnt, uint32_t &ypos, const RevSketch &R)
 {
@@ -382,9 +388,11 @@ __device__ uint32_t dense_flags(const uint32_t *__restrict__ X, const uint32_t *
         }
     }
     wave_lds_sync();
-    // flags are 0/1 bytes: the byte sum of the lane's eight
+    // flags are 0/1 bytes: the byte sum of the lane's eight; lanes 0..31 hold
+    // the tile's first 256 entries
     const uint64_t f8 = *(const uint64_t *)&L.a.d.flag[l * XPL];
-    return wave_sum32((uint32_t)((f8 * 0x0101010101010101ull) >> 56));
+    const uint32_t c = (uint32_t)((f8 * 0x0101010101010101ull) >> 56);
+    return wave_sum32(l < WAVE / 2 ? c | (c << 16) : c);
 }
 
 // np (a power of two, 64..NPIV) pivots of Y[ylo, yhi) in LDS: bucket k is
@@ -432,7 +440,8 @@ __device__ __forceinline__ void pivot_buckets(const HubLds &L, uint32_t np, cons
 // entry in Y[ylo, yhi) (which must hold every match; pivots of B entries per
 // bucket in LDS): a lockstep LDS search over the pivots, then a branchless
 // search inside the bucket, SEARCH_ILP entries per lane at a time.  Returns
-// the number flagged; lb0 receives the lower bound in N(t) of the tile's first
+// the number flagged (plus 2^16 times the number among the tile's first 256
+// entries); lb0 receives the lower bound in N(t) of the tile's first
 // entry.  Matches are also counted in R.rc (reverse start hints stay unknown).
 // The tile's entries are left in LDS (xs) as by dense_flags.
 __device__ uint32_t search_flags(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y, uint32_t ylo,
@@ -471,8 +480,12 @@ __device__ uint32_t search_flags(const uint32_t *__restrict__ X, const uint32_t 
             const uint32_t i = (h + k) * WAVE + l;
             const bool hit = i < cnt && p[k] < yhi && Y[p[k]] == x[k];
             L.a.d.flag[i] = hit ? 1 : 0;
-            c += hit ? 1u : 0u;
-            if (R.rseg && hit) atomicAdd(&R.rc[p[k] / R.rseg], 1u);
+            c += hit ? (h + k < 4 ? 0x10001u : 1u) : 0u;  // rows 0..3: the tile's first 256 entries
+            if (R.rseg && hit) {
+                const uint32_t q = p[k] / R.rseg;
+                atomicAdd(&R.rc[q], 1u);
+                if (p[k] - q * R.rseg < R.rseg / 2) atomicAdd(&R.r1[q], 1u);
+            }
             if (h + k == 0) first = p[k];
         }
     }
@@ -558,12 +571,14 @@ __device__ __forceinline__ uint16_t *sketch_row(const Exec &E, uint32_t v, uint3
 }
 
 // Reverse sketch to collect while merging a cold move at v (a hub) from t.
-__device__ __forceinline__ uint16_t *rev_setup(const Exec &E, const WS &st, uint32_t *rc, uint32_t *rh, RevSketch &R)
+__device__ __forceinline__ uint16_t *rev_setup(const Exec &E, const WS &st, uint32_t *rc, uint32_t *rh, uint32_t *r1,
+                                               RevSketch &R)
 {
     R.rseg = 0;
     R.shift = hint_shift(st.vd);
     R.rc = rc;
     R.rh = rh;
+    R.r1 = r1;
     if (st.td < E.g.memo_min) return nullptr;
     const uint32_t tsub = (st.td + TX - 1) / TX;
     const uint32_t tG = (tsub + NSUPER - 1) / NSUPER;
@@ -591,11 +606,13 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     if (E.g.memo && !W && pos_t != SENT && dv >= E.g.memo_min) row = sketch_row(E, st.v, pos_t);
     bool warm = false;
     // per segment (lane): count + 1; where its stream of N(t) may start (SENT:
-    // unknown), and an index at or above that start
-    uint32_t known = 1, ystart = SENT, ycap = td;
+    // unknown), and an index at or above that start; first-half count + 1 (0:
+    // unknown)
+    uint32_t known = 1, ystart = SENT, ycap = td, halfv = 0;
     if (row) {
         if ((uint32_t)l < nsup) {
             known = row[l];
+            halfv = row[2 * MEMO_SEGS + l];
             const uint32_t h = row[MEMO_SEGS + l];
             if (h) {
                 ystart = (h - 1) << hs;
@@ -617,11 +634,12 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     } else {
         RevSketch R;
         uint16_t *rrow = nullptr;
-        if (row) rrow = rev_setup(E, st, L.a.d.rc, L.a.d.rh, R);
+        if (row) rrow = rev_setup(E, st, L.a.d.rc, L.a.d.rh, L.a.d.r1, R);
         else R.rseg = 0;
         if (R.rseg) {
             L.a.d.rc[l] = 0;
             L.a.d.rh[l] = 0;
+            L.a.d.r1[l] = 0;
         }
         // N(t) much longer than N(v): search N(v)'s entries in it instead of
         // streaming it (reverse start hints then stay unknown)
@@ -632,7 +650,8 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         S = 0;
         for (uint32_t sp = 0; sp < nsup; ++sp) {
             uint64_t sum = 0;
-            uint32_t csp = 0;
+            uint32_t csp = 0, c1 = 0;  // members in the segment and in its first half
+            const uint32_t mid = sp * seglen + seglen / 2;
             if ((uint32_t)l == sp) ystart = ypos;
             const uint32_t sub_end = nsub < (sp + 1) * G ? nsub : (sp + 1) * G;
             for (uint32_t sub = sp * G; sub < sub_end; ++sub) {
@@ -646,23 +665,31 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
                 } else {
                     c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
                 }
-                sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, c);
-                csp += c;
+                const uint32_t ct = c & 0xFFFFu;
+                sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, ct);
+                csp += ct;
+                // the half boundary is a tile start or 256 entries into a tile
+                c1 += j0 + cnt <= mid ? ct : (j0 < mid ? c >> 16 : 0u);
                 wave_lds_sync();
             }
             if (l == 0) L.b.csum[sp] = sum;
-            if ((uint32_t)l == sp) mine = csp;
+            if ((uint32_t)l == sp) {
+                mine = csp;
+                halfv = W ? 0u : c1 + 1;
+            }
             S += sum;
         }
         if (row && (uint32_t)l < nsup) {
             __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
             __builtin_nontemporal_store((uint16_t)((ystart >> hs) + 1), row + MEMO_SEGS + l);
+            __builtin_nontemporal_store((uint16_t)halfv, row + 2 * MEMO_SEGS + l);
         }
         ycap = ystart;
         const uint32_t rsup = R.rseg ? (td + R.rseg - 1) / R.rseg : 0;
         if (rrow && (uint32_t)l < rsup) {
             __builtin_nontemporal_store((uint16_t)(L.a.d.rc[l] + 1), rrow + l);
             __builtin_nontemporal_store((uint16_t)L.a.d.rh[l], rrow + MEMO_SEGS + l);
+            __builtin_nontemporal_store((uint16_t)(L.a.d.r1[l] + 1), rrow + 2 * MEMO_SEGS + l);
         }
     }
     wave_lds_sync();
@@ -685,19 +712,31 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     // the matches of segment spx lie in N(t)[ypos, yend): from its start to
     // (at or above) the next segment's start
     const uint32_t x0 = spx * seglen;
+    const uint32_t xe = dv - x0 < seglen ? dv : x0 + seglen;
+    const uint32_t mid = xe - x0 < seglen / 2 ? xe : x0 + seglen / 2;
     uint32_t ypos = lane_val(ystart, (int)spx);
     if (ypos == SENT) ypos = td ? wave_lower_bound(Y, td, X[x0]) : 0;
     if (ypos > td) ypos = td;
     uint32_t yend = spx + 1 < nsup ? lane_val(ycap, (int)spx + 1) : td;
     if (yend < ypos) yend = ypos;
-    const uint32_t xlen = dv - x0 < seglen ? dv - x0 : seglen;
-    const bool srch = (uint64_t)(yend - ypos) > (uint64_t)E.search_ratio * xlen;
+    // with the first half's count known, only the half holding r is recomputed
+    uint32_t xa = x0, xb = xe;
+    const uint32_t hk = lane_val(halfv, (int)spx);
+    if (hk != 0 && !W && mid < xe) {
+        const uint64_t p1 = seg_pi(J, pos_t, x0, mid - x0, hk - 1);
+        if (base + p1 > r) {
+            xb = mid;
+        } else {
+            base += p1;
+            xa = mid;
+            ypos += wave_lower_bound(Y + ypos, yend - ypos, X[mid]);
+        }
+    }
+    const bool srch = (uint64_t)(yend - ypos) > (uint64_t)E.search_ratio * (xb - xa);
     const uint32_t B = srch ? load_pivots(Y, ypos, yend, L, NPIV) : 0;
-    const RevSketch none = {0, 0, nullptr, nullptr};
-    const uint32_t sub_end = nsub < (spx + 1) * G ? nsub : (spx + 1) * G;
-    for (uint32_t sub = spx * G; sub < sub_end; ++sub) {
-        const uint32_t j0 = sub * TX;
-        const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
+    const RevSketch none = {0, 0, nullptr, nullptr, nullptr};
+    for (uint32_t j0 = xa; j0 < xb; j0 += TX) {
+        const uint32_t cnt = xb - j0 < (uint32_t)TX ? xb - j0 : (uint32_t)TX;
         if (srch) {
             uint32_t lb0;
             search_flags(X, Y, ypos, yend, NPIV, B, L, j0, cnt, none, lb0);
@@ -832,16 +871,24 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
         const uint32_t G = (nsub + NSUPER - 1) / NSUPER;
         const uint32_t nsup = (nsub + G - 1) / G;
         const uint32_t seglen = G * TX;
-        uint32_t *cnt = (uint32_t *)L.b.dl;
+        uint32_t *cnt = (uint32_t *)L.b.dl, *cnt1 = cnt + NSUPER;
         cnt[l] = 0;
+        cnt1[l] = 0;
         wave_lds_sync();
         for (uint32_t k = l; k < c; k += WAVE) {
             const uint32_t q = L.a.sp.pos[k];
-            if (q != st.pos_t) atomicAdd(&cnt[q / seglen], 1u);
+            if (q != st.pos_t) {
+                const uint32_t sg = q / seglen;
+                atomicAdd(&cnt[sg], 1u);
+                if (q - sg * seglen < seglen / 2) atomicAdd(&cnt1[sg], 1u);
+            }
         }
         wave_lds_sync();
-        if ((uint32_t)l < nsup)
-            __builtin_nontemporal_store((uint16_t)(cnt[l] + 1), sketch_row(E, st.v, st.pos_t) + l);
+        if ((uint32_t)l < nsup) {
+            uint16_t *row = sketch_row(E, st.v, st.pos_t);
+            __builtin_nontemporal_store((uint16_t)(cnt[l] + 1), row + l);
+            __builtin_nontemporal_store((uint16_t)(cnt1[l] + 1), row + 2 * MEMO_SEGS + l);
+        }
         wave_lds_sync();
     }
     int64_t dsum = 0;
@@ -900,6 +947,7 @@ struct BlkLds {
     uint32_t ycap[NSUPER];   // an index at or above each segment's start
     uint32_t rc[NSUPER];     // reverse sketch counts
     uint32_t rh[NSUPER];     // reverse sketch hints
+    uint32_t r1[NSUPER];     // reverse sketch first-half counts
     uint64_t part[HWAVES];   // tile sums of one locate round
     uint32_t q;              // dequeued item
     uint32_t warm;
@@ -951,13 +999,14 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
         B.ycap[l] = yc;
         B.rc[l] = 0;
         B.rh[l] = 0;
+        B.r1[l] = 0;
         if (l == 0) B.warm = warm;
     }
     __syncthreads();
     if (!B.warm) {
         RevSketch R;
         uint16_t *rrow = nullptr;
-        if (row) rrow = rev_setup(E, st, B.rc, B.rh, R);
+        if (row) rrow = rev_setup(E, st, B.rc, B.rh, B.r1, R);
         else R.rseg = 0;
         const uint32_t sp0 = wv * nsup / HWAVES, sp1 = (wv + 1) * nsup / HWAVES;
         const bool srch = (uint64_t)td > (uint64_t)E.search_ratio * dv;
@@ -975,10 +1024,10 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
                     uint32_t c;
                     if (srch) {
                         uint32_t lb0;
-                        c = search_flags(X, Y, 0, td, NPIV, Bp, L, j0, cnt, R, lb0);
+                        c = search_flags(X, Y, 0, td, NPIV, Bp, L, j0, cnt, R, lb0) & 0xFFFFu;
                         if (sub == sp * G) ys = lb0;
                     } else {
-                        c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
+                        c = dense_flags(X, Y, td, L, j0, cnt, ypos, R) & 0xFFFFu;
                     }
                     sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, c);
                     csp += c;
@@ -1000,6 +1049,7 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
         if (wv == 0 && rrow && (uint32_t)l < rsup) {
             __builtin_nontemporal_store((uint16_t)(B.rc[l] + 1), rrow + l);
             __builtin_nontemporal_store((uint16_t)B.rh[l], rrow + MEMO_SEGS + l);
+            __builtin_nontemporal_store((uint16_t)(B.r1[l] + 1), rrow + 2 * MEMO_SEGS + l);
         }
     }
     // every wavefront finds the same segment from the shared sums
@@ -1031,11 +1081,11 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
             uint32_t cc;
             if (lsrch) {
                 uint32_t lb0;
-                cc = search_flags(X, Y, ylo, yhi, NPIV, Bl, L, j0, cnt, none, lb0);
+                cc = search_flags(X, Y, ylo, yhi, NPIV, Bl, L, j0, cnt, none, lb0) & 0xFFFFu;
             } else {
                 uint32_t ypos = ylo;
                 if (sub != spx * G) ypos = ylo + wave_lower_bound(Y + ylo, yhi - ylo, X[j0]);
-                cc = dense_flags(X, Y, td, L, j0, cnt, ypos, none);
+                cc = dense_flags(X, Y, td, L, j0, cnt, ypos, none) & 0xFFFFu;
             }
             tsum = W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, cc);
         }

@@ -150,7 +150,7 @@ def test_workgroup_hub_class(weighted, memo):
         assert first_mismatch(got, want) is None, (t_wg, search, first_mismatch(got, want))
     if memo and not weighted:
         torch.cuda.synchronize()
-        n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128), 101)
+        n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192), 101)
         assert n > 100
         g.detach_memo()
 
@@ -279,21 +279,22 @@ def hint_shift(d):
 
 def check_sketch_rows(og, memo, min_deg, limit=6000, seed=1):
     """Every written pair-sketch row (v, index of t in N(v)) holds, per segment of N(v), one plus the
-    number of its entries that are neighbours of t, and start hints into N(t) at or below the lower
-    bound of the segment's first entry and not below the end of the previous segment's matches;
-    unwritten rows and entries are zero."""
+    number of its entries that are neighbours of t; start hints into N(t) at or below the lower
+    bound of the segment's first entry and not below the end of the previous segment's matches; and
+    one plus the number in the segment's first half (0 where unknown). Unwritten rows and entries
+    are zero."""
     deg = og.degree()
     hub = deg >= min_deg
     hb = np.zeros(og.n + 1, dtype=np.int64)
     hb[1:] = np.cumsum(np.where(hub, deg, 0))
     rows = memo
-    assert rows.shape[0] >= hb[-1] and rows.shape[1] == 128
+    assert rows.shape[0] >= hb[-1] and rows.shape[1] == 192
     touched = np.nonzero(rows[:hb[-1]].any(axis=1))[0]
     rng = np.random.default_rng(seed)
     pick = touched if len(touched) <= limit else rng.choice(touched, limit, replace=False)
     hubs = np.nonzero(hub)[0]
     owner = hubs[np.searchsorted(hb[hubs], pick, side="right") - 1]
-    hinted = 0
+    hinted = halves = 0
     for r, v in zip(pick, owner):
         pos = int(r - hb[v])
         nv = og.row(v)
@@ -305,7 +306,12 @@ def check_sketch_rows(og, memo, min_deg, limit=6000, seed=1):
         want = np.add.reduceat(com.astype(np.int64), firsts) + 1
         got = rows[r, :64]
         assert np.array_equal(got[:nsup], want), (int(v), t, got[:nsup], want)
-        assert not got[nsup:].any() and not rows[r, 64 + nsup:].any(), (int(v), t)
+        assert not got[nsup:].any() and not rows[r, 64 + nsup:128].any() and not rows[r, 128 + nsup:].any()
+        half = np.array([int(com[a:min(a + seglen // 2, len(nv))].sum()) for a in firsts]) + 1
+        hv = rows[r, 128:128 + nsup].astype(np.int64)
+        hknown = hv > 0
+        halves += int(hknown.sum())
+        assert np.array_equal(hv[hknown], half[hknown]), (int(v), t, hv, half)
         hs = hint_shift(len(nt))
         lb = np.searchsorted(nt, nv[firsts], side="left")
         ub_prev = np.concatenate([[0], np.searchsorted(nt, nv[firsts[1:] - 1], side="right")])
@@ -314,7 +320,7 @@ def check_sketch_rows(og, memo, min_deg, limit=6000, seed=1):
         hinted += int(known.sum())
         assert np.all((ub_prev >> hs)[known] <= h[known] - 1), (int(v), t)
         assert np.all(h[known] - 1 <= (lb >> hs)[known]), (int(v), t)
-    assert hinted > 0
+    assert hinted > 0 and halves > 0
     return len(touched)
 
 
@@ -334,7 +340,7 @@ def test_pair_sketch_contents(mode, t_wg, search):
     starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
     got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=100000, t_wg=t_wg, search_ratio=search)
     torch.cuda.synchronize()
-    memo = g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128)
+    memo = g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192)
     n = check_sketch_rows(og, memo, 41)
     say(f"[walk] sketches mode={mode}: {n} rows written")
     assert n > 1000
@@ -356,9 +362,9 @@ def test_pair_sketches_above_degree_threshold(mode):
     deg = og.degree()
     got_bytes = g.attach_memo(budget=full // 3)
     T = g.memo_min_degree
-    assert 41 < T < 2 ** 20 and got_bytes == int(deg[deg >= T].sum()) * 256 <= full // 3
+    assert 41 < T < 2 ** 20 and got_bytes == int(deg[deg >= T].sum()) * 384 <= full // 3
     # the smaller power of two would not have fit
-    assert T // 2 <= 41 or int(deg[deg >= T // 2].sum()) * 256 > full // 3
+    assert T // 2 <= 41 or int(deg[deg >= T // 2].sum()) * 384 > full // 3
     hubs = np.argsort(deg)[-256:].astype(np.uint32)
     starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
     want = oracle_walk(og, starts, 20, 0.25, 4.0, 8, d_rule=40)
@@ -366,13 +372,13 @@ def test_pair_sketches_above_degree_threshold(mode):
     got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=4)
     assert first_mismatch(got, want) is None
     torch.cuda.synchronize()
-    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128), T)
+    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192), T)
     assert n > 100
     g.detach_memo()
     assert g.attach_memo() == full
     got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=4)
     assert first_mismatch(got, want) is None
     torch.cuda.synchronize()
-    assert check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 128), 41) > 100
+    assert check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192), 41) > 100
     g.detach_memo()
     assert g.attach_memo(budget=0) == 0
