@@ -195,7 +195,8 @@ int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, u
  * exact number of members of N(t) in each of 64 equal segments of N(v) and in
  * each segment's first half (as count + 1; 0 = unknown), and for each segment
  * a hint where its merge may start in N(t).  A later move along the same pair
- * then recomputes half a segment instead of the whole intersection.  A merge for (t -> v) also
+ * then recomputes half a segment instead of the whole intersection.  Rows
+ * of degree above 4,161,536 (127 x 512 x 64) keep no sketches.  A merge for (t -> v) also
  * fills the sketch of (v -> t) when t has degree > d_rule.  Results never
  * depend on the sketches: unknown entries are recomputed, and every known
  * entry is exact (hints never point past the segment's first candidate).

@@ -21,6 +21,9 @@ constexpr int WAVE = 64;
 // (MEMO_ROW u16 per sketch).
 constexpr int MEMO_SEGS = 64;
 constexpr int MEMO_ROW = 3 * MEMO_SEGS;
+// Sketches serve rows of at most this degree: 127 tiles of 512 entries per
+// segment, so count + 1 always fits the u16 entries.
+constexpr uint32_t MEMO_MAX_DEG = 127u * 512u * MEMO_SEGS;
 // Walk counters a graph hands out round-robin to persistent launches: up to
 // this many launches on one graph may overlap.
 constexpr int CURSOR_SLOTS = 64;

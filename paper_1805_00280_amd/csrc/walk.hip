@@ -579,7 +579,7 @@ __device__ __forceinline__ uint16_t *rev_setup(const Exec &E, const WS &st, uint
     R.rc = rc;
     R.rh = rh;
     R.r1 = r1;
-    if (st.td < E.g.memo_min) return nullptr;
+    if (st.td < E.g.memo_min || st.td > MEMO_MAX_DEG) return nullptr;
     const uint32_t tsub = (st.td + TX - 1) / TX;
     const uint32_t tG = (tsub + NSUPER - 1) / NSUPER;
     R.rseg = tG * TX;
@@ -603,7 +603,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     const uint32_t seglen = G * TX;
     const uint32_t hs = hint_shift(td);
     uint16_t *row = nullptr;
-    if (E.g.memo && !W && pos_t != SENT && dv >= E.g.memo_min) row = sketch_row(E, st.v, pos_t);
+    if (E.g.memo && !W && pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) row = sketch_row(E, st.v, pos_t);
     bool warm = false;
     // per segment (lane): count + 1; where its stream of N(t) may start (SENT:
     // unknown), and an index at or above that start; first-half count + 1 (0:
@@ -733,13 +733,14 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         }
     }
     const bool srch = (uint64_t)(yend - ypos) > (uint64_t)E.search_ratio * (xb - xa);
-    const uint32_t B = srch ? load_pivots(Y, ypos, yend, L, NPIV) : 0;
+    const uint32_t np = pivots_for(xb - xa);
+    const uint32_t B = srch ? load_pivots(Y, ypos, yend, L, np) : 0;
     const RevSketch none = {0, 0, nullptr, nullptr, nullptr};
     for (uint32_t j0 = xa; j0 < xb; j0 += TX) {
         const uint32_t cnt = xb - j0 < (uint32_t)TX ? xb - j0 : (uint32_t)TX;
         if (srch) {
             uint32_t lb0;
-            search_flags(X, Y, ypos, yend, NPIV, B, L, j0, cnt, none, lb0);
+            search_flags(X, Y, ypos, yend, np, B, L, j0, cnt, none, lb0);
         } else {
             dense_flags(X, Y, td, L, j0, cnt, ypos, none);
         }
@@ -866,7 +867,7 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
     // the positions give the sketch's per-segment counts (start hints stay
     // unknown), so later moves along this pair take the dense path's one-segment
     // recompute instead of searching again
-    if (E.g.memo && !E.g.wt && st.pos_t != SENT && dv >= E.g.memo_min) {
+    if (E.g.memo && !E.g.wt && st.pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) {
         const uint32_t nsub = (dv + TX - 1) / TX;
         const uint32_t G = (nsub + NSUPER - 1) / NSUPER;
         const uint32_t nsup = (nsub + G - 1) / G;
@@ -973,7 +974,7 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
     const uint32_t seglen = G * TX;
     const uint32_t hs = hint_shift(td);
     uint16_t *row = nullptr;
-    if (E.g.memo && !W && pos_t != SENT && dv >= E.g.memo_min) row = sketch_row(E, st.v, pos_t);
+    if (E.g.memo && !W && pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) row = sketch_row(E, st.v, pos_t);
     // one wavefront reads the sketch, so that the whole group takes one branch
     // even while another group is filling the same row
     if (wv == 0) {
@@ -1123,7 +1124,7 @@ __device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx
         return weighted_scan_locate(E, J, st, L, 1u, 0u, hi64(R1, E.g.wsum[st.v]));
     }
     bool sparse = use_sparse(E, st);
-    if (sparse && E.g.memo && !E.g.wt && st.pos_t != SENT && st.vd >= E.g.memo_min) {
+    if (sparse && E.g.memo && !E.g.wt && st.pos_t != SENT && st.vd >= E.g.memo_min && st.vd <= MEMO_MAX_DEG) {
         // a sketch that an earlier move filled makes the dense path cheaper
         const uint32_t nsub = (st.vd + TX - 1) / TX;
         const uint32_t G = (nsub + NSUPER - 1) / NSUPER;
@@ -1498,7 +1499,7 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
                 // whose sketch looks unknown (first count still 0) go to them
                 big = s > 0 && st.vd > E.t_wg && !use_sparse(E, st) &&
                       !(E.g.memo && !E.g.wt && st.pos_t != SENT && st.vd >= E.g.memo_min &&
-                        sketch_row(E, st.v, st.pos_t)[0] != 0);
+                        st.vd <= MEMO_MAX_DEG && sketch_row(E, st.v, st.pos_t)[0] != 0);
                 push = !big;
             } else {
                 uint32_t j;
