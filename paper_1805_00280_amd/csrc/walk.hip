@@ -49,7 +49,7 @@ struct WS {
 
 namespace {
 
-constexpr int HCH = 512;            // weighted scan chunk: 8 entries per lane
+constexpr int HCH = 256;            // weighted scan chunk: 4 entries per lane
 constexpr int HEPL = HCH / WAVE;
 constexpr int TX = 512;             // dense merge: N(v) tile, 8 entries per lane
 constexpr int XPL = TX / WAVE;
@@ -58,9 +58,9 @@ constexpr int YPL = 8;              // dense merge: later N(t) blocks of 8 x 64 
 constexpr int YFIRST = 4;           // entries per lane of the first N(t) block of a tile
 constexpr int NSUPER = MEMO_SEGS;   // segments (sums) per hub row
 constexpr int SPCAP = 1024;         // specials (positions) held by the sparse path
-constexpr int NPIV = 512;           // pivots of an N(t) range that N(v) entries are searched in
+constexpr int NPIV = 256;           // pivots of an N(t) range that N(v) entries are searched in
 
-// LDS of one wavefront for hub moves (8 KiB).
+// LDS of one wavefront for hub moves (5.5 KiB).
 struct HubLds {
     union {
         struct {
@@ -76,9 +76,11 @@ struct HubLds {
     } a;
     union {
         uint64_t csum[NSUPER];
-        int32_t dl[HCH];
     } b;
-    uint32_t piv[NPIV];  // pivots for searching N(v) entries in N(t)
+    union {
+        int32_t dl[HCH];     // weighted scan deltas, sparse sketch counts
+        uint32_t piv[NPIV];  // pivots for searching N(v) entries in N(t)
+    } c;
 };
 
 // Lower bound of x in row[0, n) found by the whole wavefront: each round the
@@ -406,7 +408,7 @@ __device__ uint32_t load_pivots(const uint32_t *__restrict__ Y, uint32_t ylo, ui
     const uint32_t B = (ny + np - 1) / np;
     for (uint32_t k = l; k < np; k += WAVE) {
         const uint64_t lo = (uint64_t)k * B, hi = lo + B < ny ? lo + B : ny;
-        L.piv[k] = lo < ny ? Y[ylo + hi - 1] : 0xFFFFFFFFu;
+        L.c.piv[k] = lo < ny ? Y[ylo + hi - 1] : 0xFFFFFFFFu;
     }
     wave_lds_sync();
     return B;
@@ -427,13 +429,13 @@ __device__ __forceinline__ void pivot_buckets(const HubLds &L, uint32_t np, cons
 {
     const uint32_t *q[SEARCH_ILP];
 #pragma unroll
-    for (int k = 0; k < SEARCH_ILP; ++k) q[k] = L.piv;
+    for (int k = 0; k < SEARCH_ILP; ++k) q[k] = L.c.piv;
     for (uint32_t step = np >> 1; step >= 1; step >>= 1) {
 #pragma unroll
         for (int k = 0; k < SEARCH_ILP; ++k) q[k] += q[k][step - 1] < x[k] ? step : 0u;
     }
 #pragma unroll
-    for (int k = 0; k < SEARCH_ILP; ++k) p[k] = (uint32_t)(q[k] - L.piv) + (q[k][0] < x[k] ? 1u : 0u);
+    for (int k = 0; k < SEARCH_ILP; ++k) p[k] = (uint32_t)(q[k] - L.c.piv) + (q[k][0] < x[k] ? 1u : 0u);
 }
 
 // Flags the members of N(t) in the tile N(v)[j0, j0+cnt) by searching each
@@ -773,12 +775,12 @@ __device__ uint32_t weighted_scan_locate(const Exec &E, const JobCtx &J, const W
     for (uint64_t j0 = 0; j0 < dv; j0 += HCH) {
         const uint32_t cnt = (uint32_t)std::min<uint64_t>(HCH, dv - j0);
 #pragma unroll
-        for (int e = 0; e < HEPL; ++e) L.b.dl[e * WAVE + l] = 0;
+        for (int e = 0; e < HEPL; ++e) L.c.dl[e * WAVE + l] = 0;
         wave_lds_sync();
         while (kp < c) {
             const uint32_t k = kp + l;
             const bool in = k < c && L.a.sp.pos[k] < j0 + cnt;
-            if (in) L.b.dl[L.a.sp.pos[k] - j0] = special_delta(E, J, st, L.a.sp.pos[k]);
+            if (in) L.c.dl[L.a.sp.pos[k] - j0] = special_delta(E, J, st, L.a.sp.pos[k]);
             const uint32_t n_in = __popcll(ballot(in));
             kp += n_in;
             if (n_in < WAVE) break;
@@ -788,7 +790,7 @@ __device__ uint32_t weighted_scan_locate(const Exec &E, const JobCtx &J, const W
         for (int e = 0; e < HEPL; ++e) {
             const uint32_t i = e * WAVE + l;
             uint64_t pi = 0;
-            if (i < cnt) pi = (uint64_t)((int64_t)m0 * E.g.wt[st.vo + j0 + i] + L.b.dl[i]);
+            if (i < cnt) pi = (uint64_t)((int64_t)m0 * E.g.wt[st.vo + j0 + i] + L.c.dl[i]);
             const uint64_t inc = wave_incl_scan(pi);
             const uint64_t m = ballot(i < cnt && base + inc > r);
             if (m) {
@@ -872,7 +874,7 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
         const uint32_t G = (nsub + NSUPER - 1) / NSUPER;
         const uint32_t nsup = (nsub + G - 1) / G;
         const uint32_t seglen = G * TX;
-        uint32_t *cnt = (uint32_t *)L.b.dl, *cnt1 = cnt + NSUPER;
+        uint32_t *cnt = (uint32_t *)L.c.dl, *cnt1 = cnt + NSUPER;
         cnt[l] = 0;
         cnt1[l] = 0;
         wave_lds_sync();
@@ -1269,7 +1271,7 @@ __device__ __forceinline__ void ws_to_slot(const WS &st, uint32_t flags, Slot &q
 }
 
 template <class Src, bool WALKS, bool COUNTS>
-__global__ __launch_bounds__(PBLOCK, 4) void k_persistent(Exec E, Src S)
+__global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E, Src S)
 {
     __shared__ HubLds lds[PBLOCK / WAVE];
     __shared__ Slot slots[PBLOCK / WAVE][WAVE];
