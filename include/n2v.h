@@ -200,8 +200,10 @@ int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, u
  * fills the sketch of (v -> t) when t has degree > d_rule.  Results never
  * depend on the sketches: unknown entries are recomputed, and every known
  * entry is exact (hints never point past the segment's first candidate).
- * Each walk call clears them first, so no call reuses another call's work;
- * concurrent calls on one graph share them.  n2v_graph_memo_bytes returns the
+ * Attaching clears the memory, and each walk call clears it again first, so
+ * no call reuses another call's work; concurrent calls on one graph share
+ * them.  A server keeps them across its ticks and requests (sketches depend
+ * on the graph only).  Attaching synchronises the device.  n2v_graph_memo_bytes returns the
  * size (hub entries x 384 bytes; 0 for weighted graphs); n2v_graph_set_memo
  * attaches caller device memory (NULL detaches). */
 int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes);

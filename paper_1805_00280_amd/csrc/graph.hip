@@ -334,6 +334,10 @@ extern "C" int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uin
     }
     const size_t need = (size_t)g->memo_entries * MEMO_ROW * sizeof(uint16_t);
     if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
+    // all entries start unknown: servers read sketches without a walk call
+    // having cleared them first
+    N2V_HIP(hipMemset(mem, 0, bytes));
+    N2V_HIP(hipDeviceSynchronize());
     g->dg.memo = (uint16_t *)mem;
     g->memo_bytes = bytes;
     return N2V_OK;

@@ -114,3 +114,32 @@ def test_errors(graph):
     with pytest.raises(P.N2VError):
         srv.release(t)
     srv.close()
+
+
+def test_server_with_pair_sketches_from_garbage_memory():
+    # sketch memory attached with arbitrary contents starts cleared, and the server (which keeps
+    # sketches across ticks) returns the oracle's walks; the graph has many hubs (d_rule 40)
+    import ctypes as C
+    import torch
+    torch_cuda()
+    og = oracle_rmat(13, 16, 0.65, 0.15, 0.15, 5, False)
+    g = gpu_graph_from_oracle(og, d_rule=40)
+    b = C.c_size_t()
+    assert P.lib().n2v_graph_memo_bytes(g._h, C.byref(b)) == 0 and b.value > 0
+    buf = torch.full((b.value,), 0x37, dtype=torch.uint8, device="cuda")
+    assert P.lib().n2v_graph_set_memo(g._h, C.c_void_p(buf.data_ptr()), b.value) == 0
+    deg = og.degree()
+    hubs = np.argsort(deg)[-64:].astype(np.uint32)
+    reqs = [dict(starts=np.concatenate([np.repeat(hubs, 8), np.arange(i * 300, (i + 1) * 300, dtype=np.uint32)]),
+                 L=20, p=float(PQ[i % 5]), q=float(PQ[(i * 2) % 5]), seed=1000 + i) for i in range(6)]
+    srv = P.Server(g, pool_bytes=64 << 20, chunk_walks=700, max_inflight=8)
+    tickets = [srv.submit(r["starts"], r["L"], r["p"], r["q"], r["seed"]) for r in reqs]
+    done = wait_all(srv, tickets)
+    for r, t in zip(reqs, tickets):
+        got = srv.result_tensor(done[t])
+        want = O.walk(og, r["starts"], r["L"], r["p"], r["q"], r["seed"], d_rule=40, nthreads=16)["out"]
+        assert np.array_equal(got, want)
+        srv.release(t)
+    srv.close()
+    assert P.lib().n2v_graph_set_memo(g._h, None, 0) == 0
+    del buf
