@@ -610,7 +610,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     // per segment (lane): count + 1; where its stream of N(t) may start (SENT:
     // unknown), and an index at or above that start; first-half count + 1 (0:
     // unknown)
-    uint32_t known = 1, ystart = SENT, ycap = td, halfv = 0;
+    uint32_t known = 1, ystart = SENT, ycap = td, halfv = 0, segcnt = 0;
     if (row) {
         if ((uint32_t)l < nsup) {
             known = row[l];
@@ -677,6 +677,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             if (l == 0) L.b.csum[sp] = sum;
             if ((uint32_t)l == sp) {
                 mine = csp;
+                segcnt = csp;
                 halfv = W ? 0u : c1 + 1;
             }
             S += sum;
@@ -724,15 +725,32 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     // with the first half's count known, only the half holding r is recomputed
     uint32_t xa = x0, xb = xe;
     const uint32_t hk = lane_val(halfv, (int)spx);
+    const uint32_t segc = warm ? lane_val(known, (int)spx) - 1 : lane_val(segcnt, (int)spx);
+    uint32_t crange = W ? SENT : segc;  // members of N(t) in [xa, xb), when known
     if (hk != 0 && !W && mid < xe) {
         const uint64_t p1 = seg_pi(J, pos_t, x0, mid - x0, hk - 1);
         if (base + p1 > r) {
             xb = mid;
+            crange = hk - 1;
         } else {
             base += p1;
             xa = mid;
-            ypos += wave_lower_bound(Y + ypos, yend - ypos, X[mid]);
+            crange = segc - (hk - 1);
+            if (crange != 0) ypos += wave_lower_bound(Y + ypos, yend - ypos, X[mid]);
         }
+    }
+    if (crange == 0) {
+        // no member of N(t) in the range: every pi is A_out but t's own (A_ret),
+        // so the first prefix above r has a closed form
+        const uint64_t rr = r - base;
+        const uint64_t Ao = J.A_out;
+        if (pos_t >= xa && pos_t < xb) {
+            const uint64_t before = Ao * (pos_t - xa);
+            if (rr < before) return xa + (uint32_t)(rr / Ao);
+            if (rr < before + J.A_ret) return pos_t;
+            return pos_t + 1 + (uint32_t)((rr - before - J.A_ret) / Ao);
+        }
+        return xa + (uint32_t)(rr / Ao);
     }
     const bool srch = (uint64_t)(yend - ypos) > (uint64_t)E.search_ratio * (xb - xa);
     const uint32_t np = pivots_for(xb - xa);
