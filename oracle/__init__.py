@@ -46,14 +46,20 @@ def _load():
     lib.or_graph_free.restype = None
     lib.or_multipliers.argtypes = [dbl, dbl, vp]
     lib.or_multipliers.restype = i32
-    lib.or_walk.argtypes = [vp, vp, vp, u64, u64, u32, dbl, dbl, u64, u32, u32, vp, vp, vp, vp, i32]
+    lib.or_walk.argtypes = [vp, vp, vp, u64, u64, u32, dbl, dbl, u64, u32, u32, u32, vp, vp, vp, vp, i32]
     lib.or_walk.restype = i32
-    lib.or_step_hist.argtypes = [vp, u32, u32, u32, u32, u64, dbl, dbl, u64, u32, u32, vp]
+    lib.or_step_hist.argtypes = [vp, u32, u32, u32, u32, u64, dbl, dbl, u64, u32, u32, u32, vp]
     lib.or_step_hist.restype = i32
     lib.or_entry_hash.argtypes = [u64, u32, u32, u32]
     lib.or_entry_hash.restype = u64
-    lib.or_walk_cost.argtypes = [vp, vp, vp, u64, u32, dbl, dbl, u64, u32, u32, vp, vp, vp, i32]
+    lib.or_walk_cost.argtypes = [vp, vp, vp, u64, u32, dbl, dbl, u64, u32, u32, u32, vp, vp, vp, i32]
     lib.or_walk_cost.restype = i32
+    lib.or_approx_bounds.argtypes = [u64, u64, vp, u32, u32, vp, vp, vp, vp]
+    lib.or_approx_bounds.restype = None
+    lib.or_approx_gap_below.argtypes = [u64, u64, vp, u32, u32, u32]
+    lib.or_approx_gap_below.restype = i32
+    lib.or_approx_applies.argtypes = [vp, u32, u32, vp, u32, u32]
+    lib.or_approx_applies.restype = i32
     _lib = lib
     return lib
 
@@ -197,8 +203,9 @@ A_CAP = 1024
 
 
 def walk(g: CSR, starts, L, p, q, seed, walk_base=0, wids=None, d_rule=D_RULE, a_cap=A_CAP,
-         want_out=True, want_counts=False, nthreads=None):
-    """Runs the walks; returns dict(out, cnt, checksum, transitions)."""
+         want_out=True, want_counts=False, nthreads=None, approx_t=0):
+    """Runs the walks; returns dict(out, cnt, checksum, transitions).  approx_t > 0
+    applies FN-Approx (Section 3.4) with threshold 1/approx_t."""
     starts = np.ascontiguousarray(starts, dtype=np.uint32)
     count = len(starts)
     wid_arr = None if wids is None else np.ascontiguousarray(wids, dtype=np.uint64)
@@ -207,24 +214,24 @@ def walk(g: CSR, starts, L, p, q, seed, walk_base=0, wids=None, d_rule=D_RULE, a
     cs = np.zeros(1, dtype=np.uint64)
     tr = np.zeros(1, dtype=np.uint64)
     rc = _load().or_walk(g.handle, _ptr(starts), _ptr(wid_arr), walk_base, count, L, p, q, seed,
-                         d_rule, a_cap, _ptr(out), _ptr(cnt), _ptr(cs), _ptr(tr),
+                         d_rule, a_cap, approx_t, _ptr(out), _ptr(cnt), _ptr(cs), _ptr(tr),
                          nthreads or default_threads())
     if rc != 0:
         raise ValueError("bad walk arguments (p, q or a start id)")
     return {"out": out, "cnt": cnt, "checksum": int(cs[0]), "transitions": int(tr[0])}
 
 
-def step_hist(g: CSR, t, v, s, draws, p, q, seed, wid0=0, d_rule=D_RULE, a_cap=A_CAP):
+def step_hist(g: CSR, t, v, s, draws, p, q, seed, wid0=0, d_rule=D_RULE, a_cap=A_CAP, approx_t=0):
     """Counts of each neighbour index of v chosen over `draws` single moves at (t, v, s)."""
     d = int(g.off[v + 1] - g.off[v])
     hist = np.zeros(d, dtype=np.uint64)
-    rc = _load().or_step_hist(g.handle, t, v, s, wid0, draws, p, q, seed, d_rule, a_cap, _ptr(hist))
+    rc = _load().or_step_hist(g.handle, t, v, s, wid0, draws, p, q, seed, d_rule, a_cap, approx_t, _ptr(hist))
     if rc != 0:
         raise ValueError("bad step arguments")
     return hist
 
 
-def walk_cost(g: CSR, starts, wids, L, p, q, seed, d_rule=D_RULE, a_cap=A_CAP, nthreads=None):
+def walk_cost(g: CSR, starts, wids, L, p, q, seed, d_rule=D_RULE, a_cap=A_CAP, nthreads=None, approx_t=0):
     """(algorithmic bytes, moves, moves at vertices above d_rule) summed over the walks."""
     starts = np.ascontiguousarray(starts, dtype=np.uint32)
     wids = np.ascontiguousarray(wids, dtype=np.uint64)
@@ -232,10 +239,33 @@ def walk_cost(g: CSR, starts, wids, L, p, q, seed, d_rule=D_RULE, a_cap=A_CAP, n
     s = np.zeros(1, dtype=np.uint64)
     h = np.zeros(1, dtype=np.uint64)
     rc = _load().or_walk_cost(g.handle, _ptr(starts), _ptr(wids), len(starts), L, p, q, seed,
-                              d_rule, a_cap, _ptr(b), _ptr(s), _ptr(h), nthreads or default_threads())
+                              d_rule, a_cap, approx_t, _ptr(b), _ptr(s), _ptr(h), nthreads or default_threads())
     if rc != 0:
         raise ValueError("bad cost arguments")
     return int(b[0]), int(s[0]), int(h[0])
+
+
+def approx_bounds(du, dv, p, q, wlo=1, whi=1):
+    """FN-Approx bounds (Section 3.4, Eqs. 2 and 3) on the probability of a
+    move v -> x, x != u, after u -> v: (LB, UB) as Fractions."""
+    from fractions import Fraction
+    A = np.array(multipliers(p, q), dtype=np.uint32)
+    out = [np.zeros(1, dtype=np.uint64) for _ in range(4)]
+    _load().or_approx_bounds(du, dv, _ptr(A), wlo, whi, *[_ptr(o) for o in out])
+    ln, ld, un, ud = (int(o[0]) for o in out)
+    return Fraction(ln, ld), Fraction(un, ud)
+
+
+def approx_gap_below(du, dv, p, q, approx_t, wlo=1, whi=1):
+    """UB - LB < 1/approx_t, as the oracle decides it (128-bit cross-multiplication)."""
+    A = np.array(multipliers(p, q), dtype=np.uint32)
+    return bool(_load().or_approx_gap_below(du, dv, _ptr(A), wlo, whi, approx_t))
+
+
+def approx_applies(g: CSR, t, v, p, q, approx_t, d_rule=D_RULE):
+    """Whether FN-Approx draws the move at v after t from the static weights."""
+    A = np.array(multipliers(p, q), dtype=np.uint32)
+    return bool(_load().or_approx_applies(g.handle, t, v, _ptr(A), d_rule, approx_t))
 
 
 def checksum_of(out, seed, walk_ids):

@@ -310,6 +310,7 @@ typedef struct {
     const uint16_t *wt;    /* m or NULL (all weights 1) */
     uint32_t n;
     uint16_t *wmax;        /* n, derived: largest weight in the row (0 if empty) */
+    uint16_t wlo, whi;     /* derived: smallest and largest weight of the graph (1, 1 unweighted) */
 } or_graph;
 
 or_graph *or_graph_new(const uint64_t *off, const uint32_t *adj, const uint16_t *wt, uint32_t n)
@@ -326,6 +327,16 @@ or_graph *or_graph_new(const uint64_t *off, const uint32_t *adj, const uint16_t 
             if (w > m) m = w;
         }
         g->wmax[v] = m;
+    }
+    g->wlo = 1;
+    g->whi = 1;
+    if (wt && off[n] > 0) {
+        g->wlo = wt[0];
+        g->whi = wt[0];
+        for (uint64_t e = 1; e < off[n]; ++e) {
+            if (wt[e] < g->wlo) g->wlo = wt[e];
+            if (wt[e] > g->whi) g->whi = wt[e];
+        }
     }
     return g;
 }
@@ -394,13 +405,100 @@ static uint32_t or_inverse_cdf(const or_graph *g, uint64_t seed, uint32_t wid, u
     return OR_SENT; /* not reached: P_{d-1} = S > target */
 }
 
+/* ---------------------------------------------------------------------- */
+/* FN-Approx (Section 3.4, Eqs. 2 and 3).  At a popular vertex v reached   */
+/* from an unpopular vertex u, every neighbour x != u of v has a transition */
+/* probability between a lower and an upper bound that depend only on      */
+/* d_u, d_v, the multipliers and the range of edge weights; when the two    */
+/* bounds differ by less than a threshold, the move is drawn from the       */
+/* static edge weights alone (first order).  Readings:                      */
+/*   - popular means degree > d_rule (the inverse-CDF class), unpopular     */
+/*     degree <= d_rule;                                                    */
+/*   - Weight_min and Weight_max are the graph's smallest and largest edge  */
+/*     weights (1 and 1 when unweighted);                                   */
+/*   - the numerator of a neighbour x != u lies between Weight_min times    */
+/*     the smaller and Weight_max times the larger of A_com, A_out;         */
+/*   - the denominator is A_ret w_vu + sum over the other d_v - 1           */
+/*     neighbours of A_com w (c common neighbours of u and v) or A_out w   */
+/*     (the rest); c ranges over 0 .. min(d_u - 1, d_v - 1), since u's      */
+/*     neighbour v is not a neighbour of v itself (Eq. 3 writes d_u; its    */
+/*     extreme case has d_u - 1 common neighbours); the smallest and the   */
+/*     largest denominator take Weight_min and Weight_max for every weight  */
+/*     and the c that minimises or maximises the multiplier sum;           */
+/*   - LB = smallest numerator / largest denominator, UB = largest          */
+/*     numerator / smallest denominator (Eqs. 2 and 3 when                  */
+/*     1/p <= 1 <= 1/q); the threshold is 1/T for an integer T (the paper's */
+/*     1e-3 is T = 1000) and UB - LB < 1/T is decided exactly by            */
+/*     cross-multiplying in 128-bit integers;                               */
+/*   - the first-order draw is the first-move rule at v with the move's     */
+/*     own counter: inverse CDF over the weights, attempt index 0.          */
+/* ---------------------------------------------------------------------- */
+void or_approx_bounds(uint64_t du, uint64_t dv, const uint32_t A[3], uint32_t wlo, uint32_t whi,
+                      uint64_t *lb_num, uint64_t *lb_den, uint64_t *ub_num, uint64_t *ub_den)
+{
+    uint64_t a_lo = A[1] < A[2] ? A[1] : A[2];
+    uint64_t a_hi = A[1] > A[2] ? A[1] : A[2];
+    uint64_t cmax = du - 1 < dv - 1 ? du - 1 : dv - 1;
+    /* multiplier sum with c common neighbours: A_ret + c A_com + (d_v-1-c) A_out */
+    uint64_t with_none = A[0] + (dv - 1) * A[2];
+    uint64_t with_all = A[0] + cmax * A[1] + (dv - 1 - cmax) * A[2];
+    uint64_t sum_lo = with_none < with_all ? with_none : with_all;
+    uint64_t sum_hi = with_none > with_all ? with_none : with_all;
+    *lb_num = wlo * a_lo;
+    *lb_den = whi * sum_hi;
+    *ub_num = whi * a_hi;
+    *ub_den = wlo * sum_lo;
+}
+
+/* UB - LB < 1/T for degrees du, dv >= 1 (exact). */
+int or_approx_gap_below(uint64_t du, uint64_t dv, const uint32_t A[3], uint32_t wlo, uint32_t whi, uint32_t T)
+{
+    uint64_t ln, ld, un, ud;
+    or_approx_bounds(du, dv, A, wlo, whi, &ln, &ld, &un, &ud);
+    /* un/ud - ln/ld < 1/T  <=>  T (un ld - ln ud) < ud ld */
+    or_u128 diff = (or_u128)un * ld - (or_u128)ln * ud;
+    return (or_u128)T * diff < (or_u128)ud * ld;
+}
+
+/* Whether FN-Approx draws the move at v (previous vertex t, s > 0) from   */
+/* the static weights, for the threshold 1/T (T = 0: never).               */
+int or_approx_applies(const or_graph *g, uint32_t t, uint32_t v, const uint32_t A[3],
+                      uint32_t d_rule, uint32_t T)
+{
+    if (T == 0) return 0;
+    uint64_t dv = g->off[v + 1] - g->off[v], du = g->off[t + 1] - g->off[t];
+    if (dv <= d_rule || du > d_rule || du == 0) return 0;
+    return or_approx_gap_below(du, dv, A, g->wlo, g->whi, T);
+}
+
+/* First-order draw at v with counter (walk, s, 0): the first move's rule   */
+/* for a vertex of the inverse-CDF class.                                   */
+static uint32_t or_static_draw(const or_graph *g, uint64_t seed, uint32_t wid, uint32_t s, uint32_t v)
+{
+    uint64_t ov = g->off[v], d = g->off[v + 1] - ov;
+    uint32_t r[4];
+    ph(seed, wid, s, 0, 0, r);
+    uint64_t R1 = ((uint64_t)r[0] << 32) | r[1];
+    uint64_t S = 0;
+    for (uint64_t j = 0; j < d; ++j) S += g->wt ? g->wt[ov + j] : 1u;
+    uint64_t target = hi64(R1, S), P = 0;
+    for (uint64_t j = 0; j < d; ++j) {
+        P += g->wt ? g->wt[ov + j] : 1u;
+        if (P > target) return g->adj[ov + j];
+    }
+    return OR_SENT; /* not reached */
+}
+
 /* One move of walk `wid` at step s from v (previous vertex t, ignored at  */
 /* s = 0).  Returns the next vertex, or OR_SENT when v has no neighbours.  */
+/* approx_t > 0 applies FN-Approx with threshold 1/approx_t.               */
 uint32_t or_step(const or_graph *g, uint64_t seed, uint32_t wid, uint32_t s,
-                 uint32_t t, uint32_t v, const uint32_t A[3], uint32_t d_rule, uint32_t a_cap)
+                 uint32_t t, uint32_t v, const uint32_t A[3], uint32_t d_rule, uint32_t a_cap,
+                 uint32_t approx_t)
 {
     uint64_t d = g->off[v + 1] - g->off[v];
     if (d == 0) return OR_SENT;
+    if (s > 0 && or_approx_applies(g, t, v, A, d_rule, approx_t)) return or_static_draw(g, seed, wid, s, v);
     uint32_t k = 0;
     if (d <= d_rule) {
         uint32_t amax = A[0] > A[1] ? A[0] : A[1];
@@ -439,7 +537,7 @@ typedef struct {
     uint32_t L;
     uint32_t A[3];
     uint64_t seed;
-    uint32_t d_rule, a_cap;
+    uint32_t d_rule, a_cap, approx_t;
     uint32_t *out;          /* count x (L+1) or NULL */
     uint32_t *cnt;          /* n or NULL */
     uint64_t checksum;      /* accumulated under a lock-free add */
@@ -467,7 +565,7 @@ static void or_walk_task(void *p, int tid, int nth)
             local_sum += or_entry_hash(j->seed, wid, 0, v);
             uint32_t s = 0;
             for (; s < L; ++s) {
-                uint32_t x = or_step(j->g, j->seed, wid, s, t, v, j->A, j->d_rule, j->a_cap);
+                uint32_t x = or_step(j->g, j->seed, wid, s, t, v, j->A, j->d_rule, j->a_cap, j->approx_t);
                 if (x == OR_SENT) break;
                 if (row) row[s + 1] = x;
                 if (j->cnt) __atomic_fetch_add(&j->cnt[x], 1u, __ATOMIC_RELAXED);
@@ -486,10 +584,11 @@ static void or_walk_task(void *p, int tid, int nth)
 /* Runs `count` walks of L moves.  Walk i starts at starts[i] and has id    */
 /* wids[i] (or walk_base + i when wids is NULL).  out (count x (L+1), row   */
 /* major) and cnt (n, accumulated, caller zeroes it) may each be NULL.      */
+/* approx_t > 0 applies FN-Approx with threshold 1/approx_t.               */
 /* Returns 0, or -1 on bad p/q or a start id >= n.                          */
 int or_walk(const or_graph *g, const uint32_t *starts, const uint64_t *wids, uint64_t walk_base,
             uint64_t count, uint32_t L, double p, double q, uint64_t seed,
-            uint32_t d_rule, uint32_t a_cap, uint32_t *out, uint32_t *cnt,
+            uint32_t d_rule, uint32_t a_cap, uint32_t approx_t, uint32_t *out, uint32_t *cnt,
             uint64_t *checksum, uint64_t *transitions, int nthreads)
 {
     or_walk_job j;
@@ -497,7 +596,7 @@ int or_walk(const or_graph *g, const uint32_t *starts, const uint64_t *wids, uin
     if (or_multipliers(p, q, j.A) != 0) return -1;
     for (uint64_t i = 0; i < count; ++i) if (starts[i] >= g->n) return -1;
     j.g = g; j.starts = starts; j.wids = wids; j.walk_base = walk_base; j.count = count;
-    j.L = L; j.seed = seed; j.d_rule = d_rule; j.a_cap = a_cap; j.out = out; j.cnt = cnt;
+    j.L = L; j.seed = seed; j.d_rule = d_rule; j.a_cap = a_cap; j.approx_t = approx_t; j.out = out; j.cnt = cnt;
     or_parallel(or_walk_task, &j, nthreads);
     if (checksum) *checksum = j.checksum;
     if (transitions) *transitions = j.transitions;
@@ -508,14 +607,14 @@ int or_walk(const or_graph *g, const uint32_t *starts, const uint64_t *wids, uin
 /* wid0+draws-1, hist[j] counts how often neighbour j of v was chosen.       */
 int or_step_hist(const or_graph *g, uint32_t t, uint32_t v, uint32_t s, uint32_t wid0,
                  uint64_t draws, double p, double q, uint64_t seed, uint32_t d_rule,
-                 uint32_t a_cap, uint64_t *hist)
+                 uint32_t a_cap, uint32_t approx_t, uint64_t *hist)
 {
     uint32_t A[3];
     if (or_multipliers(p, q, A) != 0) return -1;
     uint64_t base = g->off[v], d = g->off[v + 1] - base;
     if (d == 0) return -1;
     for (uint64_t i = 0; i < draws; ++i) {
-        uint32_t x = or_step(g, seed, wid0 + (uint32_t)i, s, t, v, A, d_rule, a_cap);
+        uint32_t x = or_step(g, seed, wid0 + (uint32_t)i, s, t, v, A, d_rule, a_cap, approx_t);
         uint64_t lo = base, hi = base + d;
         while (lo < hi) {
             uint64_t mid = lo + (hi - lo) / 2;
@@ -586,15 +685,29 @@ static uint64_t seg_search(or_segset *s, const uint32_t *adj, uint64_t lo, uint6
 /* Bytes of one move (returns 0 for a walk that has ended). */
 uint64_t or_step_cost(const or_graph *g, uint64_t seed, uint32_t wid, uint32_t s,
                       uint32_t t, uint32_t v, const uint32_t A[3], uint32_t d_rule, uint32_t a_cap,
-                      uint32_t *next)
+                      uint32_t approx_t, uint32_t *next)
 {
     or_segset S = {NULL, 0, 0};
     uint64_t ov = g->off[v], d = g->off[v + 1] - ov;
     seg_add(&S, SEG_OFF, (uint64_t)v * 8);
     seg_add(&S, SEG_OFF, (uint64_t)v * 8 + 8);
-    uint32_t x = or_step(g, seed, wid, s, t, v, A, d_rule, a_cap);
+    uint32_t x = or_step(g, seed, wid, s, t, v, A, d_rule, a_cap, approx_t);
     *next = x;
     if (d == 0) { free(S.v); return 0; }
+    if (s > 0 && or_approx_applies(g, t, v, A, d_rule, approx_t)) {
+        /* first-order draw: the chosen entry, and for weights the row total */
+        /* and the weights up to it (d_t is carried state)                   */
+        uint64_t lo = ov, hi = ov + d;
+        while (lo < hi) { uint64_t mid = lo + (hi - lo) / 2; if (g->adj[mid] < x) lo = mid + 1; else hi = mid; }
+        seg_add(&S, SEG_ADJ, lo * 4);
+        if (g->wt) {
+            seg_add(&S, SEG_WTOT, (uint64_t)v * 8);
+            seg_add_range(&S, SEG_WT, ov * 2, (lo + 1) * 2);
+        }
+        uint64_t c = seg_count(&S);
+        free(S.v);
+        return c * 64 + 4;
+    }
     uint32_t amax = A[0] > A[1] ? A[0] : A[1];
     if (A[2] > amax) amax = A[2];
     uint32_t acmin = A[1] < A[2] ? A[1] : A[2], acmax = A[1] > A[2] ? A[1] : A[2];
@@ -704,7 +817,7 @@ typedef struct {
     uint32_t L;
     uint32_t A[3];
     uint64_t seed;
-    uint32_t d_rule, a_cap;
+    uint32_t d_rule, a_cap, approx_t;
     uint64_t bytes, steps, hub_steps, next;
 } or_cost_job;
 
@@ -720,7 +833,7 @@ static void or_cost_task(void *p, int tid, int nth)
         uint32_t v = j->starts[i], t = OR_SENT;
         for (uint32_t s = 0; s < j->L; ++s) {
             uint32_t x;
-            uint64_t c = or_step_cost(j->g, j->seed, wid, s, t, v, j->A, j->d_rule, j->a_cap, &x);
+            uint64_t c = or_step_cost(j->g, j->seed, wid, s, t, v, j->A, j->d_rule, j->a_cap, j->approx_t, &x);
             if (x == OR_SENT) break;
             b += c;
             ++st;
@@ -738,13 +851,13 @@ static void or_cost_task(void *p, int tid, int nth)
 /* vertices of degree > d_rule over the given walks.                        */
 int or_walk_cost(const or_graph *g, const uint32_t *starts, const uint64_t *wids, uint64_t count,
                  uint32_t L, double p, double q, uint64_t seed, uint32_t d_rule, uint32_t a_cap,
-                 uint64_t *bytes, uint64_t *steps, uint64_t *hub_steps, int nthreads)
+                 uint32_t approx_t, uint64_t *bytes, uint64_t *steps, uint64_t *hub_steps, int nthreads)
 {
     or_cost_job j;
     memset(&j, 0, sizeof j);
     if (or_multipliers(p, q, j.A) != 0) return -1;
     j.g = g; j.starts = starts; j.wids = wids; j.count = count; j.L = L; j.seed = seed;
-    j.d_rule = d_rule; j.a_cap = a_cap;
+    j.d_rule = d_rule; j.a_cap = a_cap; j.approx_t = approx_t;
     or_parallel(or_cost_task, &j, nthreads);
     *bytes = j.bytes; *steps = j.steps; *hub_steps = j.hub_steps;
     return 0;

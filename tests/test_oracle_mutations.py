@@ -33,10 +33,25 @@ MUTATIONS = [
      "u |= (quad >> 1) << (scale - 1 - l);", "u |= (quad & 1u) << (scale - 1 - l);"),
     ("weight of the wrong pair",
      "ph(gseed, lo, hi, 0, 2, r);", "ph(gseed, lo, lo, 0, 2, r);"),
+    ("FN-Approx: d_u common neighbours as Eq. 3 prints",
+     "uint64_t cmax = du - 1 < dv - 1 ? du - 1 : dv - 1;", "uint64_t cmax = du < dv - 1 ? du : dv - 1;"),
+    ("FN-Approx: return multiplier dropped",
+     "uint64_t with_none = A[0] + (dv - 1) * A[2];", "uint64_t with_none = (dv - 1) * A[2];"),
+    ("FN-Approx: numerator multipliers swapped",
+     "*lb_num = wlo * a_lo;", "*lb_num = wlo * a_hi;"),
+    ("FN-Approx: weight range ignored",
+     "*ub_num = whi * a_hi;", "*ub_num = wlo * a_hi;"),
+    ("FN-Approx: threshold compared the wrong way",
+     "return (or_u128)T * diff < (or_u128)ud * ld;", "return (or_u128)T * diff > (or_u128)ud * ld;"),
+    ("FN-Approx: popular previous vertex accepted",
+     "if (dv <= d_rule || du > d_rule || du == 0) return 0;", "if (dv <= d_rule || du == 0) return 0;"),
+    ("FN-Approx: draw from the second-order law",
+     "if (s > 0 && or_approx_applies(g, t, v, A, d_rule, approx_t)) return or_static_draw(g, seed, wid, s, v);",
+     "if (s > 0 && or_approx_applies(g, t, v, A, d_rule, approx_t)) return or_inverse_cdf(g, seed, wid, s, 0, t, v, A);"),
 ]
 
 TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_rmat.py", "tests/test_oracle_law.py",
-         "tests/test_oracle_invariants.py"]
+         "tests/test_oracle_invariants.py", "tests/test_oracle_approx.py"]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
