@@ -1774,7 +1774,7 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
         return;
     }
     o->mode = N2V_MODE_AUTO;
-    o->t_wave = 256;
+    o->t_wave = 1024;
     o->t_sparse = 1023;
     o->sparse_ratio = 2;
     o->waves_per_cu = 0;

@@ -8,6 +8,7 @@ R-MAT graphs here stand in for both.  Starts are every vertex repeated r times
 """
 from __future__ import annotations
 
+import re
 from dataclasses import dataclass
 
 import numpy as np
@@ -67,6 +68,63 @@ C4 = Workload("rmat22-serving", 22, 16, *RMAT_DEFAULT, 22, False, 1.0, 1.0, 1, 8
 C5 = Workload("rmat27-p2-q0.5-r1-L80-counts", 27, 16, *RMAT_DEFAULT, 27, False, 2.0, 0.5, 1, 80, 5)
 
 ALL = {w.name: w for w in (C1, C2, C3, C4, C5)}
+
+
+# The paper's synthetic families (Section 4.1), walked as in its measurements:
+# one 80-move walk from every vertex.  Its |E| counts stored (directed) CSR
+# entries: Table 1 lists ER-20 with 10.5M edges and maximum degree 29, Skew-1
+# with 419.4M edges and maximum degree 159, which a symmetrized graph of
+# edge_factor * 2^K generated edges matches with edge factors 5 and 50 (mean
+# degrees 10 and 100), not 10 and 100.
+PAPER_PQ = ((0.5, 2.0), (2.0, 0.5))
+
+
+def _tag(x: float) -> str:
+    return f"{x:g}"
+
+
+def skew(S: float, p: float = 0.5, q: float = 2.0) -> Workload:
+    """Skew-S: 2^22 vertices, mean degree 100, b = c = 1/4 and d = S * a."""
+    a = 0.5 / (1.0 + S)
+    return Workload(f"skew{_tag(S)}-p{_tag(p)}-q{_tag(q)}-r1-L80", 22, 50, a, 0.25, 0.25, 22, False, p, q, 1, 80, 6)
+
+
+def wec(K: int, p: float = 0.5, q: float = 2.0) -> Workload:
+    """WeC-K: 2^K vertices, 100 * 2^K entries, (a, b, c, d) = (.18, .25, .25, .32)."""
+    return Workload(f"wec{K}-p{_tag(p)}-q{_tag(q)}-r1-L80", K, 50, 0.18, 0.25, 0.25, K, False, p, q, 1, 80, 7)
+
+
+def er(K: int, p: float = 0.5, q: float = 2.0) -> Workload:
+    """ER-K: 2^K vertices, mean degree 10, uniform quadrants."""
+    return Workload(f"er{K}-p{_tag(p)}-q{_tag(q)}-r1-L80", K, 5, 0.25, 0.25, 0.25, K, False, p, q, 1, 80, 8)
+
+
+def paper_family(name: str, p: float = 0.5, q: float = 2.0) -> Workload:
+    """'skew<S>', 'wec<K>' or 'er<K>' (for example 'skew3', 'wec22', 'er26')."""
+    m = re.fullmatch(r"(skew|wec|er)([0-9]+(?:\.[0-9]+)?)", name)
+    if not m:
+        raise ValueError(f"not a paper workload name: {name!r}")
+    fam, x = m.group(1), m.group(2)
+    if fam == "skew":
+        return skew(float(x), p, q)
+    if "." in x:
+        raise ValueError(f"{fam} takes an integer scale: {name!r}")
+    return (wec if fam == "wec" else er)(int(x), p, q)
+
+
+# Table 1 of the paper (|E| and maximum degree of its generated graphs, made by
+# another generator, so order-of-magnitude targets only).
+PAPER_TABLE1 = {
+    "er20": (10.5e6, 29), "er22": (41.9e6, 31), "er24": (167.8e6, 31), "er26": (671.1e6, 32),
+    "er28": (2.7e9, 33), "er30": (10.7e9, 35),
+    "wec20": (104.8e6, 1053), "wec22": (419.4e6, 1745), "wec26": (6.7e9, 2771),
+    "skew1": (419.4e6, 159), "skew2": (419.4e6, 2098), "skew3": (419.4e6, 8420),
+    "skew4": (419.2e6, 23594), "skew5": (418.3e6, 36914),
+}
+
+# FN-Base seconds on the paper's 12-machine cluster for all-vertex 80-step
+# walks at p = 0.5, q = 2 (Section 4.4): other hardware, context only.
+PAPER_FN_BASE_SECONDS = {"skew1.78": 314.5, "skew2": 369.3, "skew3": 811.1, "skew4": 1710.4, "skew5": 2913.4}
 
 
 def serving_requests(count: int, n: int, seed: int = 4, max_log2: int = 20):

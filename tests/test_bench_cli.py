@@ -44,3 +44,18 @@ def test_profiles_name_their_commands_and_kernel():
     assert "rocprofv3 --pmc FETCH_SIZE" in txt and "rocprofv3 --pmc WRITE_SIZE" in txt
     trace = open(os.path.join(ROOT, "profiles", "k_persistent_rmat24skew_kernel_trace.txt")).read()
     assert "rocprofv3 --kernel-trace --stats" in trace and "k_persistent" in trace
+
+
+def test_unknown_workload_name_exits_with_a_message():
+    r = run_bench(["--workload", "skewy"])
+    assert r.returncode == 2 and r.stdout == "" and "not a paper workload" in r.stderr
+    r = run_bench(["--workload", "er20.5"])
+    assert r.returncode == 2 and "integer scale" in r.stderr
+
+
+def test_paper_context_names_the_papers_figures():
+    from paper_1805_00280_amd import workloads as WL
+    c = bench.paper_context(WL.skew(3.0))
+    assert c["fn_base_seconds"] == 811.1 and c["table1_max_degree"] == 8420
+    assert "fn_base_seconds" not in bench.paper_context(WL.skew(3.0, 2.0, 0.5))
+    assert bench.paper_context(WL.C3) == {}

@@ -54,6 +54,28 @@ def test_scale24_skewed_workload():
     assert _run(WL.C3, 256, True) > 0
 
 
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,pq", [("skew5", (0.5, 2.0)), ("skew1.78", (2.0, 0.5))])
+def test_paper_skew_workloads(name, pq):
+    # the paper's most skewed family member and WeC-22's twin, at full size
+    assert _run(WL.paper_family(name, *pq), 512, True) > 0
+
+
+def test_paper_families_against_table1():
+    # order-of-magnitude targets: the paper's graphs came from another generator
+    torch = torch_cuda()
+    for name in ("skew1", "skew2", "skew3", "skew4", "skew5", "wec22", "er22", "er24"):
+        w = WL.paper_family(name)
+        g = P.Graph.from_rmat(*w.rmat_args(), weighted=False, device="cuda")
+        dmax = int((g.off[1:] - g.off[:-1]).max().item())
+        m_paper, d_paper = WL.PAPER_TABLE1[name]
+        say(f"[table1] {name}: m={g.m} ({m_paper:.4g}), max degree {dmax} ({d_paper})")
+        assert abs(g.m - m_paper) / m_paper < 0.01
+        assert d_paper / 2 <= dmax <= 2 * d_paper
+        del g
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
 def test_counts_workload_shape(mode):
     # the scale-27 counts workload's parameters (p=2, q=1/2, r=1, L=80, chunks

@@ -1,0 +1,36 @@
+"""The paper's synthetic graph families (Section 4.1) as generated here: names,
+quadrant probabilities, and the edge-count reading checked against Table 1 on
+the one family member small enough for the CPU oracle in a second."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1805_00280_amd import workloads as WL
+
+
+def test_family_parameters():
+    w = WL.paper_family("skew3")
+    assert (w.scale, w.edge_factor, w.r, w.L, w.p, w.q) == (22, 50, 1, 80, 0.5, 2.0)
+    d = 1.0 - w.a - w.b - w.c
+    assert w.b == w.c == 0.25 and d == pytest.approx(3.0 * w.a)
+    # WeC-22 is Skew-1.78 up to rounding of its quadrant probabilities
+    s, c = WL.paper_family("skew1.78"), WL.paper_family("wec22")
+    assert abs(s.a - c.a) < 1e-3 and (s.scale, s.edge_factor) == (c.scale, c.edge_factor)
+    e = WL.paper_family("er26", 2.0, 0.5)
+    assert (e.a, e.b, e.c, e.edge_factor, e.p, e.q) == (0.25, 0.25, 0.25, 5, 2.0, 0.5)
+    assert e.name == "er26-p2-q0.5-r1-L80"
+    for bad in ("skew", "er", "wec20.5", "c3", "skew-2"):
+        with pytest.raises(ValueError):
+            WL.paper_family(bad)
+
+
+def test_er20_matches_table1():
+    # Table 1: ER-20 has 10.5M edges and maximum degree 29; the symmetrized
+    # reading (edge factor 5, both directions stored) reproduces both.
+    w = WL.er(20)
+    og = O.rmat_csr(*w.rmat_args(), weighted=False, nthreads=8)
+    deg = np.diff(og.off.astype(np.int64))
+    m_paper, dmax_paper = WL.PAPER_TABLE1["er20"]
+    assert abs(og.m - m_paper) / m_paper < 0.01
+    assert abs(int(deg.max()) - dmax_paper) <= 3
+    assert abs(deg.mean() - 10.0) < 0.05
