@@ -52,7 +52,7 @@ extern "C" {
 #endif
 
 #define N2V_SENT 0xFFFFFFFFu
-#define N2V_ABI_VERSION 5
+#define N2V_ABI_VERSION 6
 
 enum {
     N2V_OK = 0,
@@ -189,6 +189,24 @@ int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, u
                 uint32_t L, float p, float q, uint64_t seed, const n2v_exec_opts *opts,
                 int outputs, uint32_t *out, uint32_t *cnt, uint64_t *checksum, void *ws,
                 size_t ws_bytes, void *stream);
+
+/* FN-Approx (Section 3.4, Eqs. 2 and 3): as n2v_walk_ex, except that a move
+ * at a vertex v of degree > d_rule whose previous vertex t has degree <=
+ * d_rule is drawn from the static edge weights (the rule of a first move:
+ * inverse CDF over w_vx with attempt index 0 and the move's own counter) when
+ * the bounds of Eqs. 2 and 3 on the probability of a neighbour x != t differ
+ * by less than 1/approx_t.  The bounds hold for every (p, q): the numerator
+ * lies between wlo min(A_com, A_out) and whi max(A_com, A_out), the
+ * denominator between wlo and whi times the extremes of A_ret + c A_com +
+ * (d_v - 1 - c) A_out over c = 0 .. min(d_t, d_v) - 1 common neighbours,
+ * with wlo and whi the graph's smallest and largest edge weights; the
+ * comparison is exact (128-bit cross-multiplication).  approx_t = 0 is the
+ * exact rule (identical to n2v_walk_ex); the paper's threshold 1e-3 is
+ * approx_t = 1000.  Errors as n2v_walk_ex. */
+int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
+                    uint32_t L, float p, float q, uint64_t seed, uint32_t approx_t,
+                    const n2v_exec_opts *opts, int outputs, uint32_t *out, uint32_t *cnt,
+                    uint64_t *checksum, void *ws, size_t ws_bytes, void *stream);
 
 /* Pair sketches (unweighted graphs): memory in which walk calls memoise,
  * for every traversed move (t -> v) at a vertex v of degree > d_rule, the

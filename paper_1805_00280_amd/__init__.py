@@ -30,7 +30,7 @@ EXPORTS = [
     "n2v_graph_opts_default", "n2v_graph_workspace", "n2v_graph_create", "n2v_graph_destroy",
     "n2v_graph_info", "n2v_graph_check", "n2v_graph_memo_bytes", "n2v_graph_set_memo",
     "n2v_graph_memo_plan", "n2v_graph_set_memo_min",
-    "n2v_exec_opts_default", "n2v_walk", "n2v_walk_workspace", "n2v_walk_ex",
+    "n2v_exec_opts_default", "n2v_walk", "n2v_walk_workspace", "n2v_walk_ex", "n2v_walk_approx",
     "n2v_autotune_workspace", "n2v_autotune",
     "n2v_server_opts_default", "n2v_server_create", "n2v_server_destroy", "n2v_submit", "n2v_poll",
     "n2v_release", "n2v_server_stats",
@@ -77,7 +77,7 @@ class Result(C.Structure):
                 ("start_ns", C.c_uint64), ("done_ns", C.c_uint64)]
 
 
-ABI_VERSION = 5  # layout of the option structs and sketch rows
+ABI_VERSION = 6  # layout of the option structs and sketch rows, entry points
 _lib = None
 
 
@@ -111,6 +111,8 @@ def lib():
         "n2v_walk": ([vp, vp, u32, u32, f32, f32, u64, vp, vp], i32),
         "n2v_walk_workspace": ([vp, u32, u32, P(ExecOpts), P(sz)], i32),
         "n2v_walk_ex": ([vp, vp, u32, u64, u32, f32, f32, u64, P(ExecOpts), i32, vp, vp, vp, vp, sz, vp], i32),
+        "n2v_walk_approx": ([vp, vp, u32, u64, u32, f32, f32, u64, u32, P(ExecOpts), i32, vp, vp, vp, vp, sz, vp],
+                            i32),
         "n2v_autotune_workspace": ([vp, u32, u32, P(sz)], i32),
         "n2v_autotune": ([vp, u32, u32, f32, f32, vp, sz, vp, P(ExecOpts), P(C.c_double)], i32),
         "n2v_server_opts_default": ([P(ServerOpts)], None),
@@ -283,8 +285,20 @@ class Graph:
         check(lib().n2v_walk_workspace(self._h, n_starts, L, C.byref(opts), C.byref(ws)), "n2v_walk_workspace")
         return ws.value
 
-    def walk(self, starts, L, p, q, seed, walk_base=0, out=None, opts=None, stream=None, ws=None, **kw):
-        """Walk matrix (int32 view of uint32), n_starts x (L+1)."""
+    def _walk_call(self, starts, n, walk_base, L, p, q, seed, approx_t, o, outputs, out, cnt, checksum, ws, need,
+                   stream):
+        wsp, wsn = (_ptr(ws), ws.numel()) if need else (None, 0)
+        if approx_t:
+            check(lib().n2v_walk_approx(self._h, _ptr(starts), n, walk_base, L, p, q, seed, approx_t, C.byref(o),
+                                        outputs, _ptr(out), _ptr(cnt), _ptr(checksum), wsp, wsn, _stream(stream)),
+                  "n2v_walk_approx")
+        else:
+            check(lib().n2v_walk_ex(self._h, _ptr(starts), n, walk_base, L, p, q, seed, C.byref(o), outputs,
+                                    _ptr(out), _ptr(cnt), _ptr(checksum), wsp, wsn, _stream(stream)), "n2v_walk_ex")
+
+    def walk(self, starts, L, p, q, seed, walk_base=0, out=None, opts=None, stream=None, ws=None, approx_t=0, **kw):
+        """Walk matrix (int32 view of uint32), n_starts x (L+1).  approx_t > 0
+        applies FN-Approx with threshold 1/approx_t (n2v_walk_approx)."""
         torch = _torch()
         n = int(starts.numel())
         if out is None:
@@ -293,9 +307,8 @@ class Graph:
         need = self.walk_workspace(n, L, o)
         if need and ws is None:
             ws = _alloc(need, self.device)
-        check(lib().n2v_walk_ex(self._h, _ptr(starts), n, walk_base, L, p, q, seed, C.byref(o), OUT_WALKS,
-                                _ptr(out), None, None, _ptr(ws) if need else None, ws.numel() if need else 0,
-                                _stream(stream)), "n2v_walk_ex")
+        self._walk_call(starts, n, walk_base, L, p, q, seed, approx_t, o, OUT_WALKS, out, None, None, ws, need,
+                        stream)
         return out
 
     def walk_simple(self, starts, L, p, q, seed, out=None, stream=None):
@@ -307,7 +320,7 @@ class Graph:
         return out
 
     def walk_counts(self, starts, L, p, q, seed, cnt, checksum, walk_base=0, out=None, opts=None, stream=None,
-                    ws=None, **kw):
+                    ws=None, approx_t=0, **kw):
         """Adds visit counts into cnt (int32[n]) and the checksum into checksum (int64[1])."""
         n = int(starts.numel())
         o = opts if opts is not None else exec_opts(self, **kw)
@@ -315,9 +328,8 @@ class Graph:
         if need and ws is None:
             ws = _alloc(need, self.device)
         outputs = OUT_COUNTS | (OUT_WALKS if out is not None else 0)
-        check(lib().n2v_walk_ex(self._h, _ptr(starts), n, walk_base, L, p, q, seed, C.byref(o), outputs,
-                                _ptr(out), _ptr(cnt), _ptr(checksum), _ptr(ws) if need else None,
-                                ws.numel() if need else 0, _stream(stream)), "n2v_walk_ex")
+        self._walk_call(starts, n, walk_base, L, p, q, seed, approx_t, o, outputs, out, cnt, checksum, ws, need,
+                        stream)
 
     def autotune(self, n_walks, L, p, q, stream=None):
         ws = C.c_size_t()

@@ -63,6 +63,7 @@ struct DevGraph {
     uint32_t d_rule;
     uint32_t memo_min;     // vertices of at least this degree (> d_rule) have sketch rows
     uint32_t a_cap;
+    uint32_t wlo, whi;     // smallest and largest edge weight of the graph (1, 1 unweighted)
 };
 
 // ------------------------------------------------------------ counter RNG

@@ -41,12 +41,15 @@ __global__ __launch_bounds__(256) void k_validate(const uint64_t *__restrict__ o
 __global__ __launch_bounds__(256) void k_derive(const uint64_t *__restrict__ off, const uint32_t *__restrict__ adj,
                                                 const uint16_t *__restrict__ wt, uint32_t n, VRec *__restrict__ vrec,
                                                 uint2 *__restrict__ erec, uint64_t *__restrict__ wsum,
-                                                uint32_t *__restrict__ bad, int check_sym)
+                                                uint32_t *__restrict__ bad, uint32_t *__restrict__ wrange,
+                                                int check_sym)
 {
     const int l = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / WAVE;
     uint32_t flags = 0;
+    // graph-wide weight range: wrange[0] = max(0xFFFF - w), wrange[1] = max(w)
+    uint32_t winv = 0, wall = 0;
     for (uint64_t v = wave; v < n; v += nw) {
         const uint64_t lo = off[v], hi = off[v + 1];
         uint32_t wm = 0;
@@ -60,6 +63,7 @@ __global__ __launch_bounds__(256) void k_derive(const uint64_t *__restrict__ off
             erec[e] = make_uint2(x, found ? (uint32_t)(p - xlo) : SENT);
             const uint32_t w = wt ? wt[e] : 1u;
             wm = w > wm ? w : wm;
+            winv = 0xFFFFu - w > winv ? 0xFFFFu - w : winv;
             ws += w;
         }
 #pragma unroll
@@ -68,6 +72,7 @@ __global__ __launch_bounds__(256) void k_derive(const uint64_t *__restrict__ off
             wm = o > wm ? o : wm;
         }
         ws = wave_sum(ws);
+        wall = wm > wall ? wm : wall;
         if (l == 0) {
             VRec r;
             r.off = lo;
@@ -76,6 +81,15 @@ __global__ __launch_bounds__(256) void k_derive(const uint64_t *__restrict__ off
             vrec[v] = r;
             if (wsum) wsum[v] = ws;
         }
+    }
+#pragma unroll
+    for (int msk = 32; msk >= 1; msk >>= 1) {
+        const uint32_t o = __shfl_xor(winv, msk, WAVE);
+        winv = o > winv ? o : winv;
+    }
+    if (l == 0) {
+        if (winv) atomicMax(wrange, winv);
+        if (wall) atomicMax(wrange + 1, wall);
     }
     if (flags) atomicOr(bad, flags);
 }
@@ -199,7 +213,7 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
                              bad);
     }
     hipLaunchKernelGGL(k_derive, dim3(grid_for_waves(n)), dim3(256), 0, st, off, adj, wt, n, L.vrec, L.erec, L.wsum,
-                       L.status + 1, o.validate >= 2 ? 1 : 0);
+                       L.status + 1, L.status + 2, o.validate >= 2 ? 1 : 0);
     N2V_HIP(hipGetLastError());
     if (o.validate >= 2) {
         uint32_t bad = 0;
@@ -213,7 +227,9 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
     int rc = exclusive_scan_u64(L.hbase, (uint64_t)n + 1, L.scan, st);
     if (rc) return rc;
     uint64_t hub_entries = 0;
+    uint32_t wrange[2] = {0, 0};
     N2V_HIP(hipMemcpyAsync(&hub_entries, L.hbase + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    N2V_HIP(hipMemcpyAsync(wrange, L.status + 2, sizeof(wrange), hipMemcpyDeviceToHost, st));
     N2V_HIP(hipStreamSynchronize(st));
     n2v_graph *g = (n2v_graph *)calloc(1, sizeof(n2v_graph));
     if (!g) return set_error(N2V_ENOMEM, "n2v_graph_create: host allocation failed");
@@ -236,6 +252,12 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
     g->dg.d_rule = o.d_rule;
     g->dg.memo_min = memo_min > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)memo_min;
     g->dg.a_cap = o.a_cap;
+    g->dg.wlo = 1;
+    g->dg.whi = 1;
+    if (wt && m > 0) {
+        g->dg.wlo = 0xFFFFu - wrange[0];
+        g->dg.whi = wrange[1];
+    }
     g->off = off;
     g->weighted = wt != nullptr;
     g->validate = o.validate;

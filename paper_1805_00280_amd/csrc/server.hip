@@ -264,6 +264,7 @@ struct n2v_server {
                 jr.c.k1 = (uint32_t)(r.seed >> 32);
                 jr.c.A_ret = r.A_ret;
                 jr.c.A_out = r.A_out;
+                jr.c.approx_t = 0;
                 jr.starts = r.d_starts + r.next;
                 jr.n = k;
                 h->jstart[nj] = total;

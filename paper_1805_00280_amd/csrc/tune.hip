@@ -76,6 +76,7 @@ extern "C" int n2v_autotune(n2v_graph *g, uint32_t n_walks, uint32_t L, float p,
     c.k1 = 0;
     c.A_ret = A_ret;
     c.A_out = A_out;
+    c.approx_t = 0;
 
     hipEvent_t e0, e1;
     N2V_HIP(hipEventCreate(&e0));

@@ -1132,6 +1132,30 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
 // Inverse CDF of one move by a wavefront (state uniform across lanes).
 // xj receives the chosen neighbour when the evaluation already holds it, else
 // SENT.
+// FN-Approx (Section 3.4, Eqs. 2 and 3).  At a vertex v of degree > d_rule
+// reached from a vertex t of degree <= d_rule, every neighbour x != t of v has
+// a probability between LB = wlo min(A_com, A_out) / (whi S_hi) and
+// UB = whi max(A_com, A_out) / (wlo S_lo), where S_lo and S_hi bound the
+// multiplier sum A_ret + c A_com + (d_v - 1 - c) A_out over c = 0 ..
+// min(d_t, d_v) - 1 common neighbours and wlo, whi are the graph's smallest
+// and largest weights.  When UB - LB < 1/approx_t the move is drawn as a first
+// move (static weights, attempt 0, the move's own counter).  The comparison
+// T (UB_n LB_d - LB_n UB_d) < UB_d LB_d is exact in 128 bits.
+__device__ __forceinline__ bool approx_first_order(const Exec &E, const JobCtx &J, const WS &st)
+{
+    if (!J.approx_t || st.s == 0 || st.vd <= E.g.d_rule || st.td > E.g.d_rule || st.td == 0) return false;
+    const uint64_t dv = st.vd, ac = 4, ao = J.A_out;
+    const uint64_t c = (st.td < st.vd ? st.td : st.vd) - 1;
+    const uint64_t none = J.A_ret + (dv - 1) * ao;
+    const uint64_t all = J.A_ret + c * ac + (dv - 1 - c) * ao;
+    const uint64_t lb_n = (uint64_t)E.g.wlo * (ac < ao ? ac : ao);
+    const uint64_t lb_d = (uint64_t)E.g.whi * (none > all ? none : all);
+    const uint64_t ub_n = (uint64_t)E.g.whi * (ac > ao ? ac : ao);
+    const uint64_t ub_d = (uint64_t)E.g.wlo * (none < all ? none : all);
+    const unsigned __int128 diff = (unsigned __int128)ub_n * lb_d - (unsigned __int128)lb_n * ub_d;
+    return (unsigned __int128)J.approx_t * diff < (unsigned __int128)ub_d * lb_d;
+}
+
 __device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &st_in, uint32_t kidx,
                                                      HubLds &L, uint32_t &xj)
 {
@@ -1139,7 +1163,7 @@ __device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx
     const WS st = uniform_ws(st_in);
     const R4 rr = philox(J.k0, J.k1, J.wbase + st.i, st.s, kidx, 0u);
     const uint64_t R1 = join64(rr.x, rr.y);
-    if (st.s == 0) {
+    if (st.s == 0 || approx_first_order(E, J, st)) {
         if (!E.g.wt) return (uint32_t)hi64(R1, st.vd);
         return weighted_scan_locate(E, J, st, L, 1u, 0u, hi64(R1, E.g.wsum[st.v]));
     }
@@ -1517,7 +1541,7 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
                 item = i;
                 // workgroups pay off on full merges: with sketches, only moves
                 // whose sketch looks unknown (first count still 0) go to them
-                big = s > 0 && st.vd > E.t_wg && !use_sparse(E, st) &&
+                big = s > 0 && st.vd > E.t_wg && !use_sparse(E, st) && !approx_first_order(E, S.c, st) &&
                       !(E.g.memo && !E.g.wt && st.pos_t != SENT && st.vd >= E.g.memo_min &&
                         st.vd <= MEMO_MAX_DEG && sketch_row(E, st.v, st.pos_t)[0] != 0);
                 push = !big;
@@ -1795,9 +1819,10 @@ extern "C" int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_
     return N2V_OK;
 }
 
-extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
-                           uint32_t L, float p, float q, uint64_t seed, const n2v_exec_opts *opts, int outputs,
-                           uint32_t *out, uint32_t *cnt, uint64_t *checksum, void *ws, size_t ws_bytes, void *stream)
+extern "C" int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
+                               uint32_t L, float p, float q, uint64_t seed, uint32_t approx_t,
+                               const n2v_exec_opts *opts, int outputs, uint32_t *out, uint32_t *cnt,
+                               uint64_t *checksum, void *ws, size_t ws_bytes, void *stream)
 {
     if (!g) return set_error(N2V_EINVAL, "n2v_walk: null graph");
     if (L < 1) return set_error(N2V_EINVAL, "n2v_walk: L must be >= 1");
@@ -1829,6 +1854,7 @@ extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t 
     S.c.k1 = (uint32_t)(seed >> 32);
     S.c.A_ret = A_ret;
     S.c.A_out = A_out;
+    S.c.approx_t = approx_t;
     S.starts = starts;
     S.n = n_starts;
     S.cur = E.cursor;
@@ -1851,6 +1877,14 @@ extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t 
     if (W && C) return launch_persistent<true, true>(E, S, o, g->device, st);
     if (W) return launch_persistent<true, false>(E, S, o, g->device, st);
     return launch_persistent<false, true>(E, S, o, g->device, st);
+}
+
+extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
+                           uint32_t L, float p, float q, uint64_t seed, const n2v_exec_opts *opts, int outputs,
+                           uint32_t *out, uint32_t *cnt, uint64_t *checksum, void *ws, size_t ws_bytes, void *stream)
+{
+    return n2v_walk_approx(g, starts, n_starts, walk_base, L, p, q, seed, 0, opts, outputs, out, cnt, checksum, ws,
+                           ws_bytes, stream);
 }
 
 extern "C" int n2v_walk(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint32_t L, float p, float q,

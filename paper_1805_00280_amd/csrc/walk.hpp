@@ -28,6 +28,7 @@ struct JobCtx {
     uint32_t L;
     uint32_t k0, k1;               // Philox key = seed
     uint32_t A_ret, A_out;         // 4/p and 4/q
+    uint32_t approx_t;             // FN-Approx threshold 1/approx_t (0: exact)
 };
 
 // One job of a serving table: its context plus its start ids.

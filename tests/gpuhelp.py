@@ -46,9 +46,9 @@ def gpu_walk(g, starts_np, L, p, q, seed, walk_base=0, **opts):
     return u32(out)
 
 
-def oracle_walk(og, starts_np, L, p, q, seed, walk_base=0, d_rule=1024, a_cap=1024, wids=None):
+def oracle_walk(og, starts_np, L, p, q, seed, walk_base=0, d_rule=1024, a_cap=1024, wids=None, approx_t=0):
     return O.walk(og, starts_np, L, p, q, seed, walk_base=walk_base, wids=wids, d_rule=d_rule, a_cap=a_cap,
-                  nthreads=16)["out"]
+                  nthreads=16, approx_t=approx_t)["out"]
 
 
 def first_mismatch(a, b):

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.n2v_abi_version() == 5
+    assert lib.n2v_abi_version() == 6
 
 
 def test_defaults(lib):

@@ -382,3 +382,63 @@ def test_pair_sketches_above_degree_threshold(mode):
     assert check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192), 41) > 100
     g.detach_memo()
     assert g.attach_memo(budget=0) == 0
+
+
+# ------------------------------------------------------------------ FN-Approx
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN, "plain_wg"])
+def test_fn_approx_matches_oracle(weighted, mode):
+    # moves at vertices above d_rule reached from vertices at or below it are
+    # drawn from the static weights when the bound gap is below 1/T
+    torch_cuda()
+    og = oracle_rmat(13, 16, *SKEW, 13, False)
+    if weighted:
+        # weights in [1, 3], symmetric: a narrow range, so that the bounds meet
+        src = np.repeat(np.arange(og.n, dtype=np.int64), og.degree().astype(np.int64))
+        dst = og.adj.astype(np.int64)
+        lo, hi = np.minimum(src, dst), np.maximum(src, dst)
+        og = O.CSR(og.off, og.adj, (1 + (lo * 7 + hi * 13) % 3).astype(np.uint16))
+    g = gpu_graph_from_oracle(og, d_rule=100)
+    if not weighted:
+        g.attach_memo()
+    deg = og.degree()
+    hubs = np.argsort(deg)[-64:].astype(np.uint32)
+    starts = np.concatenate([np.repeat(hubs, 8), np.arange(og.n, dtype=np.uint32)])
+    kw = dict(mode=P.MODE_PLAIN, t_wg=0) if mode == "plain_wg" else dict(mode=mode)
+    cases = [((0.5, 2.0), 100), ((2.0, 0.5), 1000), ((0.25, 4.0), 30), ((4.0, 0.25), 300), ((1.0, 0.5), 1)]
+    if weighted:
+        cases = [((0.5, 2.0), 30), ((2.0, 0.5), 100), ((0.25, 1.0), 20)]
+    for (p, q), T in cases:
+        say(f"[approx] weighted={weighted} mode={mode} p={p} q={q} T={T}")
+        want = oracle_walk(og, starts, 30, p, q, 17, d_rule=100, approx_t=T)
+        exact = oracle_walk(og, starts, 30, p, q, 17, d_rule=100)
+        assert (want != exact).any(axis=1).sum() > 100  # the rule is exercised
+        got = gpu_walk(g, starts, 30, p, q, 17, approx_t=T, **kw)
+        assert first_mismatch(got, want) is None, (p, q, T, first_mismatch(got, want))
+    # threshold 0 is the exact rule
+    got = gpu_walk(g, starts, 30, 0.5, 2.0, 17, approx_t=0, **kw)
+    want = oracle_walk(og, starts, 30, 0.5, 2.0, 17, d_rule=100)
+    assert first_mismatch(got, want) is None, first_mismatch(got, want)
+
+
+def test_fn_approx_big_hubs_and_counts():
+    torch = torch_cuda()
+    og = _two_hub_graph()
+    g = gpu_graph_from_oracle(og, d_rule=64)
+    g.attach_memo()
+    starts = np.concatenate([np.repeat(np.arange(6, dtype=np.uint32), 40), np.arange(2, 3000, dtype=np.uint32)])
+    for T in (1000, 20000):
+        want = oracle_walk(og, starts, 12, 0.5, 2.0, 3, d_rule=64, approx_t=T)
+        for kw in (dict(), dict(sparse_ratio=100000, search_ratio=0), dict(mode=P.MODE_PLAIN, t_wg=0)):
+            say(f"[approx] big hubs T={T} {kw}")
+            got = gpu_walk(g, starts, 12, 0.5, 2.0, 3, approx_t=T, **kw)
+            assert first_mismatch(got, want) is None, (T, kw, first_mismatch(got, want))
+    ref = O.walk(og, starts, 12, 0.5, 2.0, 3, d_rule=64, approx_t=1000, want_out=False, want_counts=True,
+                 nthreads=16)
+    for mode in (P.MODE_PERSISTENT, P.MODE_PLAIN):
+        cnt = torch.zeros(og.n, dtype=torch.int32, device="cuda")
+        cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+        g.walk_counts(starts_tensor(torch, starts), 12, 0.5, 2.0, 3, cnt, cs, mode=mode, approx_t=1000)
+        torch.cuda.synchronize()
+        assert np.array_equal(u32(cnt), ref["cnt"])
+        assert int(cs.cpu().numpy().view(np.uint64)[0]) == ref["checksum"]
