@@ -208,6 +208,16 @@ int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint32_t n_start
                     const n2v_exec_opts *opts, int outputs, uint32_t *out, uint32_t *cnt,
                     uint64_t *checksum, void *ws, size_t ws_bytes, void *stream);
 
+/* Visit profile (the frequency-versus-degree study of Section 3.3): for
+ * visit counts cnt (device, n uint32, as written by the COUNTS output),
+ * vertices[k] and visits[k] (device, nbuckets uint64 each, overwritten)
+ * receive the number of vertices and their summed visits in degree bucket k:
+ * bucket 0 holds degree 0, bucket k >= 1 degrees in ((k-1) width, k width],
+ * and bucket nbuckets-1 also every larger degree.  width >= 1, 2 <= nbuckets
+ * <= 2048, else N2V_EINVAL.  Asynchronous on `stream`. */
+int n2v_visit_profile(const n2v_graph *g, const uint32_t *cnt, uint32_t width, uint32_t nbuckets,
+                      uint64_t *vertices, uint64_t *visits, void *stream);
+
 /* Pair sketches (unweighted graphs): memory in which walk calls memoise,
  * for every traversed move (t -> v) at a vertex v of degree > d_rule, the
  * exact number of members of N(t) in each of 64 equal segments of N(v) and in

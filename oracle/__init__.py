@@ -268,6 +268,18 @@ def approx_applies(g: CSR, t, v, p, q, approx_t, d_rule=D_RULE):
     return bool(_load().or_approx_applies(g.handle, t, v, _ptr(A), d_rule, approx_t))
 
 
+def visit_profile(g: CSR, cnt, width, nbuckets):
+    """Vertices and summed visits per equi-width degree bucket (Section 3.3,
+    the frequency-versus-degree figure): bucket 0 is degree 0, bucket k >= 1
+    degrees in ((k-1) width, k width], the last bucket also every larger degree."""
+    deg = np.diff(g.off.astype(np.int64))
+    b = np.minimum(-(-deg // width), nbuckets - 1)
+    verts = np.bincount(b, minlength=nbuckets).astype(np.int64)
+    visits = np.zeros(nbuckets, dtype=np.int64)
+    np.add.at(visits, b, np.asarray(cnt, dtype=np.int64))
+    return verts, visits
+
+
 def checksum_of(out, seed, walk_ids):
     """Visit counts and checksum of a walk matrix, entry by entry (slow; small inputs)."""
     total = 0

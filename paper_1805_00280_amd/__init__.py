@@ -31,6 +31,7 @@ EXPORTS = [
     "n2v_graph_info", "n2v_graph_check", "n2v_graph_memo_bytes", "n2v_graph_set_memo",
     "n2v_graph_memo_plan", "n2v_graph_set_memo_min",
     "n2v_exec_opts_default", "n2v_walk", "n2v_walk_workspace", "n2v_walk_ex", "n2v_walk_approx",
+    "n2v_visit_profile",
     "n2v_autotune_workspace", "n2v_autotune",
     "n2v_server_opts_default", "n2v_server_create", "n2v_server_destroy", "n2v_submit", "n2v_poll",
     "n2v_release", "n2v_server_stats",
@@ -113,6 +114,7 @@ def lib():
         "n2v_walk_ex": ([vp, vp, u32, u64, u32, f32, f32, u64, P(ExecOpts), i32, vp, vp, vp, vp, sz, vp], i32),
         "n2v_walk_approx": ([vp, vp, u32, u64, u32, f32, f32, u64, u32, P(ExecOpts), i32, vp, vp, vp, vp, sz, vp],
                             i32),
+        "n2v_visit_profile": ([vp, vp, u32, u32, vp, vp, vp], i32),
         "n2v_autotune_workspace": ([vp, u32, u32, P(sz)], i32),
         "n2v_autotune": ([vp, u32, u32, f32, f32, vp, sz, vp, P(ExecOpts), P(C.c_double)], i32),
         "n2v_server_opts_default": ([P(ServerOpts)], None),
@@ -330,6 +332,16 @@ class Graph:
         outputs = OUT_COUNTS | (OUT_WALKS if out is not None else 0)
         self._walk_call(starts, n, walk_base, L, p, q, seed, approx_t, o, outputs, out, cnt, checksum, ws, need,
                         stream)
+
+    def visit_profile(self, cnt, width, nbuckets, stream=None):
+        """(vertices, visits) per degree bucket (int64 tensors of nbuckets): bucket 0 is
+        degree 0, bucket k degrees in ((k-1) width, k width], the last also all larger."""
+        torch = _torch()
+        verts = torch.empty(nbuckets, dtype=torch.int64, device=self.device)
+        visits = torch.empty(nbuckets, dtype=torch.int64, device=self.device)
+        check(lib().n2v_visit_profile(self._h, _ptr(cnt), width, nbuckets, _ptr(verts), _ptr(visits),
+                                      _stream(stream)), "n2v_visit_profile")
+        return verts, visits
 
     def autotune(self, n_walks, L, p, q, stream=None):
         ws = C.c_size_t()

@@ -377,6 +377,64 @@ extern "C" int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes)
     return n2v_graph_set_memo_min(g, mem, bytes, g->dg.d_rule + 1 > g->dg.d_rule ? g->dg.d_rule + 1 : g->dg.d_rule);
 }
 
+// Visit profile: vertices and summed visit counts per equi-width degree
+// bucket (bucket k >= 1 holds degrees in ((k-1) width, k width], bucket 0 the
+// isolated vertices, the last bucket everything above).  Per-block LDS
+// histograms, then one atomic per nonzero bin.
+constexpr uint32_t PROFILE_MAX_BUCKETS = 2048;
+
+__global__ __launch_bounds__(256) void k_visit_profile(const VRec *__restrict__ vrec, const uint32_t *__restrict__ cnt,
+                                                       uint32_t n, uint32_t width, uint32_t nb,
+                                                       unsigned long long *__restrict__ verts,
+                                                       unsigned long long *__restrict__ visits)
+{
+    __shared__ unsigned long long hv[PROFILE_MAX_BUCKETS], hc[PROFILE_MAX_BUCKETS];
+    for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) {
+        hv[k] = 0;
+        hc[k] = 0;
+    }
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint64_t d = vrec[v].deg;
+        const uint64_t k = (d + width - 1) / width;
+        const uint32_t b = k < nb - 1 ? (uint32_t)k : nb - 1;
+        atomicAdd(&hv[b], 1ull);
+        const uint32_t c = cnt[v];
+        if (c) atomicAdd(&hc[b], (unsigned long long)c);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) {
+        if (hv[k]) atomicAdd(&verts[k], hv[k]);
+        if (hc[k]) atomicAdd(&visits[k], hc[k]);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+extern "C" int n2v_visit_profile(const n2v_graph *g, const uint32_t *cnt, uint32_t width, uint32_t nbuckets,
+                                 uint64_t *vertices, uint64_t *visits, void *stream)
+{
+    if (!g || !cnt || !vertices || !visits) return set_error(N2V_EINVAL, "n2v_visit_profile: null argument");
+    if (width < 1 || nbuckets < 2 || nbuckets > PROFILE_MAX_BUCKETS)
+        return set_error(N2V_EINVAL, "n2v_visit_profile: width >= 1 and 2 <= nbuckets <= %u", PROFILE_MAX_BUCKETS);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_u64, dim3((nbuckets + 255) / 256), dim3(256), 0, st, (unsigned long long *)vertices,
+                       nbuckets);
+    hipLaunchKernelGGL(k_zero_u64, dim3((nbuckets + 255) / 256), dim3(256), 0, st, (unsigned long long *)visits,
+                       nbuckets);
+    N2V_HIP(hipGetLastError());
+    if (g->dg.n == 0) return N2V_OK;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(((uint64_t)g->dg.n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_visit_profile, dim3(blocks), dim3(256), 0, st, g->dg.vrec, cnt, g->dg.n, width, nbuckets,
+                       (unsigned long long *)vertices, (unsigned long long *)visits);
+    N2V_HIP(hipGetLastError());
+    return N2V_OK;
+}
+
 extern "C" int n2v_graph_check(const n2v_graph *g, void *stream)
 {
     if (!g) return set_error(N2V_EINVAL, "n2v_graph_check: null graph");

@@ -123,7 +123,7 @@ PAPER_TABLE1 = {
 }
 
 # FN-Base seconds on the paper's 12-machine cluster for all-vertex 80-step
-# walks at p = 0.5, q = 2 (Section 4.4): other hardware, context only.
+# walks at p = 0.5, q = 2 (Section 4.6): other hardware, context only.
 PAPER_FN_BASE_SECONDS = {"skew1.78": 314.5, "skew2": 369.3, "skew3": 811.1, "skew4": 1710.4, "skew5": 2913.4}
 
 
@@ -145,3 +145,7 @@ def serving_requests(count: int, n: int, seed: int = 4, max_log2: int = 20):
             "seed": int(rng.integers(0, 2**63)),
         })
     return out
+
+# FN-Approx speedup over FN-Base at the ends of the skew study (Section 4.6).
+PAPER_FN_APPROX_SPEEDUP = {("skew1.78", 0.5, 2.0): 1.45, ("skew5", 0.5, 2.0): 17.2,
+                           ("skew1.78", 2.0, 0.5): 1.41, ("skew5", 2.0, 0.5): 17.1}

@@ -83,3 +83,9 @@ def test_memo_calls_reject_null_arguments(lib):
     assert lib.n2v_graph_memo_plan(None, 0, C.byref(dmin), C.byref(b)) == -1
     assert lib.n2v_graph_set_memo_min(None, None, 0, 0) == -1
     assert lib.n2v_graph_memo_bytes(None, C.byref(b)) == -1
+
+
+def test_visit_profile_and_approx_reject_null_arguments(lib):
+    assert lib.n2v_visit_profile(None, None, 1, 2, None, None, None) == -1
+    assert lib.n2v_walk_approx(None, None, 0, 0, 10, C.c_float(1.0), C.c_float(1.0), 0, 1000, None, 1, None, None,
+                               None, None, 0, None) == -1

@@ -442,3 +442,29 @@ def test_fn_approx_big_hubs_and_counts():
         torch.cuda.synchronize()
         assert np.array_equal(u32(cnt), ref["cnt"])
         assert int(cs.cpu().numpy().view(np.uint64)[0]) == ref["checksum"]
+
+
+def test_visit_profile_matches_oracle_and_degree_bias():
+    # the paper's frequency-versus-degree study: mean visits per degree bucket
+    torch = torch_cuda()
+    og = oracle_rmat(14, 16, *DEF, 14, False)
+    g = gpu_graph_from_oracle(og)
+    starts = np.tile(np.arange(og.n, dtype=np.uint32), 4)
+    cnt = torch.zeros(og.n, dtype=torch.int32, device="cuda")
+    cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    g.walk_counts(starts_tensor(torch, starts), 80, 1.0, 1.0, 5, cnt, cs)
+    for width, nb in ((50, 64), (1, 2048), (1000, 2)):
+        verts, visits = g.visit_profile(cnt, width, nb)
+        torch.cuda.synchronize()
+        ov, oc = O.visit_profile(og, u32(cnt), width, nb)
+        assert np.array_equal(verts.cpu().numpy(), ov) and np.array_equal(visits.cpu().numpy(), oc), width
+    # first-order walks (p = q = 1) visit a vertex about in proportion to its degree
+    ov, oc = O.visit_profile(og, u32(cnt), 20, 64)
+    keep = ov[1:-1] >= 20
+    mid = (np.arange(1, 63) * 20 - 10)[keep]
+    mean = oc[1:-1][keep] / ov[1:-1][keep]
+    assert np.corrcoef(mid, mean)[0, 1] > 0.95
+    with pytest.raises(P.N2VError):
+        g.visit_profile(cnt, 0, 8)
+    with pytest.raises(P.N2VError):
+        g.visit_profile(cnt, 10, 4096)

@@ -126,3 +126,16 @@ def test_cost_model_counts_moves(g12):
     # at least one 64-byte segment and the 4-byte output per move
     assert b >= s * (64 + 4)
     assert 0 <= h <= s
+
+
+def test_visit_profile_buckets_by_hand():
+    # star with centre 0 of degree 7 and a separate edge 8-9; vertex 10 isolated
+    edges = [(0, i) for i in range(1, 8)] + [(8, 9)]
+    g = O.CSR.from_edges(11, edges)
+    cnt = np.array([10, 1, 1, 1, 1, 1, 1, 1, 4, 4, 3], dtype=np.uint32)
+    verts, visits = O.visit_profile(g, cnt, 3, 4)
+    # degree 0 -> bucket 0, degree 1 -> bucket 1 ((0, 3]), degree 7 -> bucket 3 (last: (6, 9] and above)
+    assert verts.tolist() == [1, 9, 0, 1]
+    assert visits.tolist() == [3, 15, 0, 10]
+    verts, visits = O.visit_profile(g, cnt, 1, 8)
+    assert verts.tolist() == [1, 9, 0, 0, 0, 0, 0, 1] and visits.tolist() == [3, 15, 0, 0, 0, 0, 0, 10]
