@@ -1324,9 +1324,11 @@ __global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E, Src S)
     const uint32_t tw = E.t_wave < E.g.d_rule ? E.t_wave : E.g.d_rule;
     uint32_t pool_next = 0, pool_end = 0;  // walks this wavefront has claimed but not started
     // claims of up to POOL walks, but small enough that every wavefront of the
-    // grid gets some (wave-class moves of a wavefront's walks run one by one)
+    // grid gets some (wave-class moves of a wavefront's walks run one by one);
+    // later claims shrink with what is left (guided self-scheduling), so that
+    // no wavefront holds unstarted walks while others have run dry
     const uint32_t nwaves = gridDim.x * (PBLOCK / WAVE);
-    const uint32_t pool = total / nwaves < 1u ? 1u : (total / nwaves < (uint32_t)POOL ? total / nwaves : (uint32_t)POOL);
+    uint32_t pool = total / nwaves < 1u ? 1u : (total / nwaves < (uint32_t)POOL ? total / nwaves : (uint32_t)POOL);
     bool exhausted = false;
     uint64_t csum = 0;
     sl[l].flags = 0;
@@ -1345,15 +1347,19 @@ __global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E, Src S)
                 if (m == 0) break;
                 if (pool_next >= pool_end) {
                     if (exhausted) break;
+                    const uint32_t want = (uint32_t)__popcll(m);
+                    const uint32_t claim = pool > want ? pool : want;
                     uint32_t b = 0;
-                    if (l == 0) b = atomicAdd(S.cursor(), pool);
+                    if (l == 0) b = atomicAdd(S.cursor(), claim);
                     b = uni(b);
                     if (b >= total) {
                         exhausted = true;
                         break;
                     }
                     pool_next = b;
-                    pool_end = total - b < pool ? total : b + pool;
+                    pool_end = total - b < claim ? total : b + claim;
+                    const uint32_t share = (total - pool_end) / (2 * nwaves);
+                    pool = share < pool ? share : pool;
                 }
                 const uint32_t avail = pool_end - pool_next;
                 const uint32_t r = __popcll(m & lanemask_lt());
