@@ -240,9 +240,9 @@ int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes);
 /* Sketches for part of the hub rows, when all of them do not fit: only moves
  * at vertices of degree >= min_degree (> d_rule) keep sketches; the other hub
  * moves take the full pass every time.  n2v_graph_memo_plan returns the
- * smallest such threshold (d_rule + 1, else a power of two) whose rows fit in
- * `budget` bytes, and those rows' bytes (*min_degree = 0xFFFFFFFF and *bytes =
- * 0 when none fit; weighted graphs: N2V_EINVAL).  It synchronises the device.
+ * smallest such threshold whose rows fit in `budget` bytes, and those rows'
+ * bytes (*min_degree = 0xFFFFFFFF and *bytes = 0 when none fit; weighted
+ * graphs: N2V_EINVAL).  It synchronises the device.
  * n2v_graph_set_memo_min attaches `bytes` of device memory (256-byte aligned)
  * for rows of degree >= min_degree; it re-indexes the rows on the default
  * stream and synchronises, so no walk on this graph may be in flight.
@@ -273,8 +273,8 @@ int n2v_autotune(n2v_graph *g, uint32_t n_walks, uint32_t L, float p, float q, v
  * into a caller-provided device pool as space frees up, cuts them into walk
  * chunks, and launches chunks of several requests together on its stream, one
  * captured graph replay (table copy plus persistent kernel) per tick.
- * Results are identical to n2v_walk_ex with walk_base = 0 on the same
- * request, alone or in any mix.
+ * Results are identical to n2v_walk_approx (n2v_walk_ex when approx_t = 0)
+ * with walk_base = 0 on the same request, alone or in any mix.
  * ---------------------------------------------------------------------- */
 typedef struct {
     uint32_t max_queue;     /* pending requests accepted before N2V_EAGAIN (default 4096) */
@@ -290,6 +290,7 @@ typedef struct {
     uint32_t L;
     float p, q;
     uint64_t seed;
+    uint32_t approx_t;  /* FN-Approx threshold 1/approx_t as in n2v_walk_approx (0: exact) */
 } n2v_request;
 
 typedef struct {

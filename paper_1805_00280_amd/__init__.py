@@ -70,7 +70,7 @@ class ServerOpts(C.Structure):
 
 class Request(C.Structure):
     _fields_ = [("host_starts", C.c_void_p), ("n_starts", C.c_uint32), ("L", C.c_uint32), ("p", C.c_float),
-                ("q", C.c_float), ("seed", C.c_uint64)]
+                ("q", C.c_float), ("seed", C.c_uint64), ("approx_t", C.c_uint32)]
 
 
 class Result(C.Structure):
@@ -388,9 +388,9 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, starts_np, L, p, q, seed):
+    def submit(self, starts_np, L, p, q, seed, approx_t=0):
         starts_np = np.ascontiguousarray(starts_np, dtype=np.uint32)
-        r = Request(starts_np.ctypes.data, len(starts_np), L, p, q, seed)
+        r = Request(starts_np.ctypes.data, len(starts_np), L, p, q, seed, approx_t)
         t = C.c_uint64()
         rc = lib().n2v_submit(self._h, C.byref(r), C.byref(t))
         check(rc, "n2v_submit")

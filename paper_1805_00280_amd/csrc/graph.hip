@@ -121,6 +121,27 @@ __global__ __launch_bounds__(256) void k_deg_hist(const uint64_t *__restrict__ o
     if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
+// Sum of the degrees >= dmin (per-block reduction, one atomic per block).
+__global__ __launch_bounds__(256) void k_deg_sum_ge(const uint64_t *__restrict__ off, uint32_t n, uint64_t dmin,
+                                                    unsigned long long *__restrict__ out)
+{
+    unsigned long long acc = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint64_t d = off[v + 1] - off[v];
+        if (d >= dmin) acc += d;
+    }
+    acc = wave_sum(acc);
+    __shared__ unsigned long long part[256 / WAVE];
+    if (lane_id() == 0) part[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < 256 / WAVE; ++i) t += part[i];
+        if (t) atomicAdd(out, t);
+    }
+}
+
 __global__ void k_zero_u32(uint32_t *p, uint32_t n)
 {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
@@ -313,19 +334,51 @@ extern "C" int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *
         if (hipMemcpy(h, hist, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
             rc = hip_fail(hipGetLastError(), "hipMemcpy");
     }
-    (void)hipFree(hist);
-    if (rc) return rc;
-    // thresholds: powers of two above d_rule; entries of rows of degree >= 2^k
-    for (int k = 0; k < 64; ++k) {
+    if (rc) {
+        (void)hipFree(hist);
+        return rc;
+    }
+    // the first power of two above d_rule whose rows fit brackets the answer:
+    // the threshold below it (half of it, or d_rule + 1) does not fit
+    uint64_t lo = 0, hi = 0, hi_e = 0;
+    for (int k = 0; k < 64 && !hi; ++k) {
         const uint64_t t = 1ull << k;
         if (t <= dmin) continue;
         uint64_t e = 0;
         for (int b = k; b < 64; ++b) e += h[b];
         if (e * row <= budget) {
-            *min_degree = (uint32_t)std::min<uint64_t>(t, 0xFFFFFFFFull);
-            *bytes = e * row;
-            return N2V_OK;
+            lo = std::max<uint64_t>(dmin, t / 2);
+            hi = t;
+            hi_e = e;
         }
+    }
+    // then the smallest threshold in (lo, hi] whose rows fit, by bisection
+    // over one-pass sums of the degrees at or above a candidate
+    while (!rc && hi && hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        unsigned long long e = 0;
+        if (hipMemset(hist, 0, sizeof(unsigned long long)) != hipSuccess) {
+            rc = hip_fail(hipGetLastError(), "hipMemset");
+            break;
+        }
+        hipLaunchKernelGGL(k_deg_sum_ge, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, mid, hist);
+        if (hipMemcpy(&e, hist, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = hip_fail(hipGetLastError(), "hipMemcpy");
+            break;
+        }
+        if (e * row <= budget) {
+            hi = mid;
+            hi_e = e;
+        } else {
+            lo = mid;
+        }
+    }
+    (void)hipFree(hist);
+    if (rc) return rc;
+    if (hi && hi <= 0xFFFFFFFFull) {
+        *min_degree = (uint32_t)hi;
+        *bytes = hi_e * row;
+        return N2V_OK;
     }
     *min_degree = 0xFFFFFFFFu;
     *bytes = 0;

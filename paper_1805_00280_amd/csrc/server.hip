@@ -45,7 +45,7 @@ enum ReqState { QUEUED, RUNNING, DONE, FAILED };
 struct Req {
     uint64_t ticket;
     std::vector<uint32_t> starts;  // host copy of the start ids until admission
-    uint32_t n, L, A_ret, A_out;
+    uint32_t n, L, A_ret, A_out, approx_t;
     uint64_t seed;
     uint64_t submit_ns = 0, start_ns = 0, done_ns = 0;
     size_t off = 0, bytes = 0;  // pool allocation
@@ -264,7 +264,7 @@ struct n2v_server {
                 jr.c.k1 = (uint32_t)(r.seed >> 32);
                 jr.c.A_ret = r.A_ret;
                 jr.c.A_out = r.A_out;
-                jr.c.approx_t = 0;
+                jr.c.approx_t = r.approx_t;
                 jr.starts = r.d_starts + r.next;
                 jr.n = k;
                 h->jstart[nj] = total;
@@ -460,6 +460,7 @@ extern "C" int n2v_submit(n2v_server *s, const n2v_request *r, uint64_t *ticket)
     q.L = r->L;
     q.A_ret = A_ret;
     q.A_out = A_out;
+    q.approx_t = r->approx_t;
     q.seed = r->seed;
     q.bytes = bytes;
     {

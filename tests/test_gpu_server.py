@@ -65,6 +65,29 @@ def test_mix_equals_oracle_and_alone(graph):
     srv.close()
 
 
+def test_mix_with_fn_approx_requests(graph):
+    # exact and FN-Approx requests in one mix: each equals the oracle's rule for it
+    og, g = graph
+    reqs = requests(og.n, 24, 3)
+    for i, r in enumerate(reqs):
+        r["approx_t"] = (0, 30, 1000)[i % 3]
+    srv = P.Server(g, pool_bytes=64 << 20, chunk_walks=700, max_inflight=16)
+    tickets = [srv.submit(r["starts"], r["L"], r["p"], r["q"], r["seed"], approx_t=r["approx_t"]) for r in reqs]
+    done = wait_all(srv, tickets)
+    changed = 0
+    for r, t in zip(reqs, tickets):
+        got = srv.result_tensor(done[t])
+        want = O.walk(og, r["starts"], r["L"], r["p"], r["q"], r["seed"], d_rule=64, nthreads=16,
+                      approx_t=r["approx_t"])["out"]
+        assert np.array_equal(got, want), r["approx_t"]
+        if r["approx_t"]:
+            exact = O.walk(og, r["starts"], r["L"], r["p"], r["q"], r["seed"], d_rule=64, nthreads=16)["out"]
+            changed += int((exact != want).any(axis=1).sum())
+        srv.release(t)
+    assert changed > 0
+    srv.close()
+
+
 def test_tiny_pool_queues_and_admits_as_memory_frees(graph):
     og, g = graph
     # room for about two requests at a time: the rest wait for releases

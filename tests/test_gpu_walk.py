@@ -363,8 +363,8 @@ def test_pair_sketches_above_degree_threshold(mode):
     got_bytes = g.attach_memo(budget=full // 3)
     T = g.memo_min_degree
     assert 41 < T < 2 ** 20 and got_bytes == int(deg[deg >= T].sum()) * 384 <= full // 3
-    # the smaller power of two would not have fit
-    assert T // 2 <= 41 or int(deg[deg >= T // 2].sum()) * 384 > full // 3
+    # the threshold is the smallest that fits
+    assert T - 1 <= 41 or int(deg[deg >= T - 1].sum()) * 384 > full // 3
     hubs = np.argsort(deg)[-256:].astype(np.uint32)
     starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
     want = oracle_walk(og, starts, 20, 0.25, 4.0, 8, d_rule=40)
