@@ -13,7 +13,7 @@ from gpuhelp import first_mismatch, oracle_rmat, say, torch_cuda, u32
 pytestmark = pytest.mark.gpu
 
 
-def _run(w, sample, attach_memo):
+def _run(w, sample, attach_memo, approx_t=0):
     torch = torch_cuda()
     say(f"[full] {w.name}: device graph")
     g = P.Graph.from_rmat(*w.rmat_args(), weighted=w.weighted, device="cuda")
@@ -26,17 +26,18 @@ def _run(w, sample, attach_memo):
     starts = torch.arange(w.walks, dtype=torch.int64, device="cuda").remainder_(w.n).to(torch.int32)
     out = torch.empty((w.walks, w.L + 1), dtype=torch.int32, device="cuda")
     say(f"[full] {w.name}: persistent pass over {w.walks} walks")
-    g.walk(starts, w.L, w.p, w.q, w.seed, out=out)
+    g.walk(starts, w.L, w.p, w.q, w.seed, out=out, approx_t=approx_t)
     torch.cuda.synchronize()
     g.check_starts()
     ids = w.sample_walk_ids(sample, seed=99)
     got = u32(out[torch.from_numpy(ids.astype(np.int64)).cuda()])
     say(f"[full] {w.name}: oracle on {len(ids)} sampled walks")
-    want = O.walk(og, (ids % w.n).astype(np.uint32), w.L, w.p, w.q, w.seed, wids=ids, nthreads=16)["out"]
+    want = O.walk(og, (ids % w.n).astype(np.uint32), w.L, w.p, w.q, w.seed, wids=ids, nthreads=16,
+                  approx_t=approx_t)["out"]
     assert first_mismatch(got, want) is None, first_mismatch(got, want)
     say(f"[full] {w.name}: plain pass")
     out2 = torch.empty_like(out)
-    g.walk(starts, w.L, w.p, w.q, w.seed, out=out2, mode=P.MODE_PLAIN)
+    g.walk(starts, w.L, w.p, w.q, w.seed, out=out2, mode=P.MODE_PLAIN, approx_t=approx_t)
     torch.cuda.synchronize()
     assert torch.equal(out, out2)
     moves = int((out[:, 1:] != -1).sum().item())
@@ -59,6 +60,12 @@ def test_scale24_skewed_workload():
 def test_paper_skew_workloads(name, pq):
     # the paper's most skewed family member and WeC-22's twin, at full size
     assert _run(WL.paper_family(name, *pq), 512, True) > 0
+
+
+@pytest.mark.timeout(900)
+def test_paper_skew5_fn_approx():
+    # FN-Approx at the paper's threshold on its most skewed graph, full size
+    assert _run(WL.skew(5.0, 2.0, 0.5), 512, True, approx_t=1000) > 0
 
 
 def test_paper_families_against_table1():

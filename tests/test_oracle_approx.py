@@ -181,3 +181,16 @@ def test_approx_walks_differ_only_at_approximated_moves():
     # threshold 0 is the exact rule
     assert np.array_equal(O.walk(og, starts, L, 0.5, 2.0, 4, d_rule=d_rule, approx_t=0)["out"],
                           O.walk(og, starts, L, 0.5, 2.0, 4, d_rule=d_rule)["out"])
+
+
+def test_distance_report_measures_the_two_laws():
+    from oracle.approx_distance import tv_distance
+    g = _hub_graph()
+    # p = q = 1: the exact law is the static-weight law
+    assert tv_distance(g, 1, 0, 1.0, 1.0) == pytest.approx(0.0, abs=1e-15)
+    # otherwise the distance equals half the L1 gap of the enumerated laws
+    for p, q in [(0.5, 2.0), (2.0, 0.5), (4.0, 0.25)]:
+        second = brute.transition_law(g.off, g.adj, None, 1, 0, p, q)
+        first = brute.transition_law(g.off, g.adj, None, 1, 0, p, q, first=True)
+        want = sum(abs(second[x] - first[x]) for x in second) / 2
+        assert tv_distance(g, 1, 0, p, q) == pytest.approx(float(want), rel=1e-12)
