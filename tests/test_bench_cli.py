@@ -59,3 +59,8 @@ def test_paper_context_names_the_papers_figures():
     assert c["fn_base_seconds"] == 811.1 and c["table1_max_degree"] == 8420
     assert "fn_base_seconds" not in bench.paper_context(WL.skew(3.0, 2.0, 0.5))
     assert bench.paper_context(WL.C3) == {}
+
+
+def test_skew_profile_names_its_commands():
+    txt = open(os.path.join(ROOT, "profiles", "k_persistent_skew5_kernel_trace.txt")).read()
+    assert txt.count("rocprofv3 --kernel-trace --stats") == 2 and "--workload skew5 --approx 1000" in txt
