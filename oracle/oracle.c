@@ -22,6 +22,10 @@
  *     vertex starts r walks; the walk length counts moves.
  *   - Section 4.1 (data sets): R-MAT picks one of the four quadrants with
  *     probabilities a, b, c, d recursively down to single cells.
+ *   - Section 3.4 (FN-Approx, Eqs. 2 and 3): at a popular vertex reached
+ *     from an unpopular one, a move whose probability bounds differ by less
+ *     than a threshold is drawn from the static weights; the readings are
+ *     listed where the rule is defined below.
  *
  * Readings of points the paper leaves open (the integer draw rule):
  *   - multipliers are integers: A_ret = 4/p, A_com = 4, A_out = 4/q, with
