@@ -1129,9 +1129,6 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
     return dv - 1;  // not reached: the last prefix equals S > r
 }
 
-// Inverse CDF of one move by a wavefront (state uniform across lanes).
-// xj receives the chosen neighbour when the evaluation already holds it, else
-// SENT.
 // FN-Approx (Section 3.4, Eqs. 2 and 3).  At a vertex v of degree > d_rule
 // reached from a vertex t of degree <= d_rule, every neighbour x != t of v has
 // a probability between LB = wlo min(A_com, A_out) / (whi S_hi) and
@@ -1156,6 +1153,9 @@ __device__ __forceinline__ bool approx_first_order(const Exec &E, const JobCtx &
     return (unsigned __int128)J.approx_t * diff < (unsigned __int128)ub_d * lb_d;
 }
 
+// Inverse CDF of one move by a wavefront (state uniform across lanes).
+// xj receives the chosen neighbour when the evaluation already holds it, else
+// SENT.
 __device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx &J, const WS &st_in, uint32_t kidx,
                                                      HubLds &L, uint32_t &xj)
 {
