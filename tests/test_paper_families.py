@@ -34,3 +34,15 @@ def test_er20_matches_table1():
     assert abs(og.m - m_paper) / m_paper < 0.01
     assert abs(int(deg.max()) - dmax_paper) <= 3
     assert abs(deg.mean() - 10.0) < 0.05
+
+
+def test_wec20_matches_table1():
+    # Table 1: WeC-20 has 104.8M edges and maximum degree 1053 (the paper's
+    # generator is another one, so the degree is an order-of-magnitude target)
+    w = WL.wec(20)
+    og = O.rmat_csr(*w.rmat_args(), weighted=False, nthreads=8)
+    deg = np.diff(og.off.astype(np.int64))
+    m_paper, dmax_paper = WL.PAPER_TABLE1["wec20"]
+    assert abs(og.m - m_paper) / m_paper < 0.005
+    assert dmax_paper / 2 <= int(deg.max()) <= 2 * dmax_paper
+    assert abs(deg.mean() - 100.0) < 0.1
