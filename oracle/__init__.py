@@ -1,7 +1,8 @@
 """CPU oracle for node2vec second-order walks (test infrastructure only).
 
-Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
-``bench.py`` import this package.  It wraps ``oracle.c`` (plain C, built with
+Only the test suite, ``__graft_entry__.smoke()``, the CPU-baseline leg of
+``bench.py`` and this package's own FN-Approx distance report
+(``oracle/approx_distance.py``) import it.  It wraps ``oracle.c`` (plain C, built with
 gcc by ``oracle/build.py``) and shares nothing with the GPU library.  See the
 header of ``oracle.c`` for the definitions each function follows.
 """
