@@ -1325,8 +1325,9 @@ __global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E, Src S)
     uint32_t pool_next = 0, pool_end = 0;  // walks this wavefront has claimed but not started
     // claims of up to POOL walks, but small enough that every wavefront of the
     // grid gets some (wave-class moves of a wavefront's walks run one by one);
-    // later claims shrink with what is left (guided self-scheduling), so that
-    // no wavefront holds unstarted walks while others have run dry
+    // later claims shrink with what is left (guided self-scheduling, down to
+    // one walk), so that no wavefront holds unstarted walks while others have
+    // run dry
     const uint32_t nwaves = gridDim.x * (PBLOCK / WAVE);
     uint32_t pool = total / nwaves < 1u ? 1u : (total / nwaves < (uint32_t)POOL ? total / nwaves : (uint32_t)POOL);
     bool exhausted = false;
@@ -1347,8 +1348,7 @@ __global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E, Src S)
                 if (m == 0) break;
                 if (pool_next >= pool_end) {
                     if (exhausted) break;
-                    const uint32_t want = (uint32_t)__popcll(m);
-                    const uint32_t claim = pool > want ? pool : want;
+                    const uint32_t claim = pool;
                     uint32_t b = 0;
                     if (l == 0) b = atomicAdd(S.cursor(), claim);
                     b = uni(b);
@@ -1359,7 +1359,7 @@ __global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E, Src S)
                     pool_next = b;
                     pool_end = total - b < claim ? total : b + claim;
                     const uint32_t share = (total - pool_end) / (2 * nwaves);
-                    pool = share < pool ? share : pool;
+                    pool = share < pool ? (share > 0 ? share : 1u) : pool;
                 }
                 const uint32_t avail = pool_end - pool_next;
                 const uint32_t r = __popcll(m & lanemask_lt());
