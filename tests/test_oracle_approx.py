@@ -194,3 +194,20 @@ def test_distance_report_measures_the_two_laws():
         first = brute.transition_law(g.off, g.adj, None, 1, 0, p, q, first=True)
         want = sum(abs(second[x] - first[x]) for x in second) / 2
         assert tv_distance(g, 1, 0, p, q) == pytest.approx(float(want), rel=1e-12)
+
+
+def test_uniform_weights_walk_like_unweighted():
+    # Scaling every weight by c changes no draw: floor(hi64(R, c S) / c) equals
+    # hi64(R, S), rejection compares u < c pi as floor(u / c) < pi, and the
+    # FN-Approx bounds are ratios of weights.  So a graph whose weights all
+    # equal 7 walks exactly like the unweighted graph, exact rule or not.
+    og = O.rmat_csr(10, 16, 0.65, 0.15, 0.15, 10, weighted=False, nthreads=8)
+    w7 = O.CSR(og.off, og.adj, np.full(og.m, 7, dtype=np.uint16))
+    starts = np.tile(np.arange(og.n, dtype=np.uint32), 3)
+    for p, q in [(0.5, 2.0), (2.0, 0.5), (0.25, 4.0)]:
+        for T in (0, 50):
+            a = O.walk(og, starts, 20, p, q, 5, d_rule=64, approx_t=T)["out"]
+            b = O.walk(w7, starts, 20, p, q, 5, d_rule=64, approx_t=T)["out"]
+            assert np.array_equal(a, b), (p, q, T)
+    exact = O.walk(og, starts, 20, 0.5, 2.0, 5, d_rule=64)["out"]
+    assert not np.array_equal(exact, O.walk(og, starts, 20, 0.5, 2.0, 5, d_rule=64, approx_t=50)["out"])
