@@ -468,3 +468,22 @@ def test_visit_profile_matches_oracle_and_degree_bias():
         g.visit_profile(cnt, 0, 8)
     with pytest.raises(P.N2VError):
         g.visit_profile(cnt, 10, 4096)
+
+
+def test_uniform_weights_walk_like_unweighted():
+    # all weights 7: the weighted kernels (weight scans, row totals) must draw
+    # exactly what the unweighted ones draw, exact rule and FN-Approx
+    torch_cuda()
+    og = oracle_rmat(12, 16, *SKEW, 12, False)
+    w7 = O.CSR(og.off, og.adj, np.full(og.m, 7, dtype=np.uint16))
+    g0 = gpu_graph_from_oracle(og, d_rule=64)
+    g7 = gpu_graph_from_oracle(w7, d_rule=64)
+    starts = np.tile(np.arange(og.n, dtype=np.uint32), 2)
+    for mode in (P.MODE_PERSISTENT, P.MODE_PLAIN):
+        for T in (0, 50):
+            say(f"[walk] uniform weights mode={mode} approx_t={T}")
+            a = gpu_walk(g0, starts, 20, 0.5, 2.0, 9, approx_t=T, mode=mode)
+            b = gpu_walk(g7, starts, 20, 0.5, 2.0, 9, approx_t=T, mode=mode)
+            assert first_mismatch(b, a) is None, (mode, T, first_mismatch(b, a))
+            want = oracle_walk(og, starts, 20, 0.5, 2.0, 9, d_rule=64, approx_t=T)
+            assert first_mismatch(a, want) is None, (mode, T, first_mismatch(a, want))
