@@ -103,6 +103,23 @@ def test_paper_case_matches_eq2():
             assert lb == Fraction(wlo) / ((ip + (dv - 1) * iq) * whi)
 
 
+def test_paper_case_matches_eq3_with_reachable_common_neighbours():
+    # Eq. 3 (1/p <= 1 <= 1/q): UB = (Wmax/q) / ((1/p + d_u + (d_v - d_u - 1)/q) Wmin)
+    # assumes d_u common neighbours; at most d_u - 1 are possible (u's
+    # neighbour v is not a neighbour of v), and with d_u - 1 in place of d_u
+    # the oracle's bound is Eq. 3 exactly, and never above Eq. 3 as printed
+    for p, q in [(1.0, 0.5), (2.0, 0.5), (4.0, 0.25), (1.0, 1.0), (2.0, 1.0)]:
+        for du, dv, wlo, whi in [(3, 5000, 1, 1), (10, 20000, 1, 1), (5, 1500, 2, 7), (1, 1025, 1, 1)]:
+            _, ub = O.approx_bounds(du, dv, p, q, wlo, whi)
+            ip, iq = 1 / Fraction(p), 1 / Fraction(q)
+
+            def eq3(c):
+                return (whi * iq) / ((ip + c + (dv - c - 1) * iq) * wlo)
+
+            assert ub == eq3(du - 1)
+            assert ub <= eq3(du)
+
+
 def test_gap_decision_is_exact_at_extreme_sizes():
     rng = np.random.default_rng(3)
     cases = [(1, 2), (1, 2**32 - 1), (1024, 2**32 - 1), (2**31, 2**32 - 1), (7, 1025), (1024, 1025)]
