@@ -89,3 +89,28 @@ def test_visit_profile_and_approx_reject_null_arguments(lib):
     assert lib.n2v_visit_profile(None, None, 1, 2, None, None, None) == -1
     assert lib.n2v_walk_approx(None, None, 0, 0, 10, C.c_float(1.0), C.c_float(1.0), 0, 1000, None, 1, None, None,
                                None, None, 0, None) == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the binding's ctypes structs against the C compiler's view of include/n2v.h
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pairs = [("n2v_rmat_params", P.RmatParams), ("n2v_graph_opts", P.GraphOpts), ("n2v_exec_opts", P.ExecOpts),
+             ("n2v_server_opts", P.ServerOpts), ("n2v_request", P.Request), ("n2v_result", P.Result)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "n2v.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, cls in pairs:
+        assert int(got[f"{cname} size"]) == C.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname} {f}"]) == getattr(cls, f).offset, (cname, f)
