@@ -52,7 +52,7 @@ extern "C" {
 #endif
 
 #define N2V_SENT 0xFFFFFFFFu
-#define N2V_ABI_VERSION 6
+#define N2V_ABI_VERSION 7
 
 enum {
     N2V_OK = 0,
@@ -133,6 +133,8 @@ int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const uint16_t *w
                      uint64_t m, const n2v_graph_opts *opts, void *ws, size_t ws_bytes,
                      void *stream, n2v_graph **out);
 
+/* Frees the handle (the caller's arrays and workspace stay the caller's).
+ * N2V_EINVAL while a server created on the graph has not been destroyed. */
 int n2v_graph_destroy(n2v_graph *g);
 
 /* Number of vertices / entries and the rule parameters of a graph. */
@@ -171,7 +173,10 @@ void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o);
 /* Walks of L moves; out (device) is n_starts x (L+1) uint32, row-major, with
  * out[i][0] = starts[i].  Uses the persistent kernel and needs no workspace.
  * Start ids >= n produce an all-N2V_SENT tail and set the graph's device
- * error flag (read with n2v_graph_check).  Calls on one graph may overlap. */
+ * error flag (read with n2v_graph_check).  Calls on one graph may overlap:
+ * each persistent launch takes one of the graph's 64 walk counters that no
+ * launch still in flight holds, and N2V_EAGAIN is returned (nothing
+ * enqueued) while all 64 are held. */
 int n2v_walk(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint32_t L, float p,
              float q, uint64_t seed, uint32_t *out, void *stream);
 
@@ -218,35 +223,48 @@ int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint32_t n_start
 int n2v_visit_profile(const n2v_graph *g, const uint32_t *cnt, uint32_t width, uint32_t nbuckets,
                       uint64_t *vertices, uint64_t *visits, void *stream);
 
-/* Pair sketches (unweighted graphs): memory in which walk calls memoise,
- * for every traversed move (t -> v) at a vertex v of degree > d_rule, the
- * exact number of members of N(t) in each of 64 equal segments of N(v) and in
- * each segment's first half (as count + 1; 0 = unknown), and for each segment
- * a hint where its merge may start in N(t).  A later move along the same pair
- * then recomputes half a segment instead of the whole intersection.  Rows
- * of degree above 4,161,536 (127 x 512 x 64) keep no sketches.  A merge for (t -> v) also
- * fills the sketch of (v -> t) when t has degree > d_rule.  Results never
- * depend on the sketches: unknown entries are recomputed, and every known
- * entry is exact (hints never point past the segment's first candidate).
- * Attaching clears the memory, and each walk call clears it again first, so
- * no call reuses another call's work; concurrent calls on one graph share
- * them.  A server keeps them across its ticks and requests (sketches depend
- * on the graph only).  Attaching synchronises the device.  n2v_graph_memo_bytes returns the
- * size (hub entries x 384 bytes; 0 for weighted graphs); n2v_graph_set_memo
- * attaches caller device memory (NULL detaches). */
+/* Pair sketches (unweighted graphs; the FN-Cache paragraph of Section 3.4
+ * keeps work done for popular vertices for reuse): memory in which walk calls
+ * memoise, for every traversed move (t -> v) at a vertex v of degree >
+ * d_rule, the exact number of members of N(t) in each of 64 equal segments
+ * of N(v) and in each segment's first half (as count + 1; 0 = unknown), and
+ * for each segment a hint where its merge may start in N(t).  A later move
+ * along the same pair then recomputes half a segment instead of the whole
+ * intersection.  Rows of degree above 4,161,536 (127 x 512 x 64) keep no
+ * sketches.  A merge for (t -> v) also fills the sketch of (v -> t) when t
+ * has degree > d_rule.  Results never depend on the sketches: unknown
+ * entries are recomputed, and every known entry is exact (hints never point
+ * past the segment's first candidate).
+ * Sketches describe the graph only (not p, q, seed or the walks), so they
+ * persist across calls: every call, and every server on the graph, reads
+ * and fills the same memory, and overlapping calls only ever write equal
+ * values into an entry.  Attaching clears the memory; n2v_graph_memo_clear
+ * makes later calls start from unknown entries again (a cold pass).
+ * n2v_graph_memo_bytes returns the size (hub entries x 384 bytes; 0 for
+ * weighted graphs); n2v_graph_set_memo attaches caller device memory (NULL
+ * detaches).  Attaching synchronises the device, and returns N2V_EINVAL,
+ * changing nothing, while a server created on the graph is alive. */
 int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes);
 int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes);
+
+/* Enqueues on `stream` the clearing of the attached sketch memory (N2V_OK
+ * with nothing to do when none is attached).  Walks still in flight on other
+ * streams may fill entries again; their results are unaffected. */
+int n2v_graph_memo_clear(n2v_graph *g, void *stream);
 
 /* Sketches for part of the hub rows, when all of them do not fit: only moves
  * at vertices of degree >= min_degree (> d_rule) keep sketches; the other hub
  * moves take the full pass every time.  n2v_graph_memo_plan returns the
  * smallest such threshold whose rows fit in `budget` bytes, and those rows'
  * bytes (*min_degree = 0xFFFFFFFF and *bytes = 0 when none fit; weighted
- * graphs: N2V_EINVAL).  It synchronises the device.
+ * graphs: N2V_EINVAL).  It allocates nothing (its degree statistics use the
+ * graph's workspace) and synchronises the device, so plans on one graph must
+ * not run concurrently.
  * n2v_graph_set_memo_min attaches `bytes` of device memory (256-byte aligned)
  * for rows of degree >= min_degree; it re-indexes the rows on the default
  * stream and synchronises, so no walk on this graph may be in flight.
- * N2V_ENOMEM if `bytes` is too small.  NULL detaches. */
+ * N2V_ENOMEM if `bytes` is too small, N2V_EINVAL while a server is alive:
+ * both leave the graph as it was.  NULL detaches. */
 int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *min_degree, size_t *bytes);
 int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uint32_t min_degree);
 

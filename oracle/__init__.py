@@ -55,6 +55,22 @@ def _load():
     lib.or_entry_hash.restype = u64
     lib.or_walk_cost.argtypes = [vp, vp, vp, u64, u32, dbl, dbl, u64, u32, u32, u32, vp, vp, vp, i32]
     lib.or_walk_cost.restype = i32
+    lib.or_step_cost.argtypes = [vp, u64, u32, u32, u32, u32, vp, u32, u32, u32, vp]
+    lib.or_step_cost.restype = u64
+    lib.or_walk_cost_classes.argtypes = [vp, vp, vp, u64, u32, dbl, dbl, u64, u32, u32, u32, vp, i32]
+    lib.or_walk_cost_classes.restype = i32
+    lib.or_memo_off_lines.argtypes = [u32]
+    lib.or_memo_off_lines.restype = u64
+    lib.or_memo_search_levels.argtypes = [u64]
+    lib.or_memo_search_levels.restype = u64
+    lib.or_memo_pair_lines.argtypes = [vp, u32, u32]
+    lib.or_memo_pair_lines.restype = u64
+    lib.or_memo_cold_lines.argtypes = [vp, i32, u32, u32]
+    lib.or_memo_cold_lines.restype = u64
+    lib.or_memo_warm_lines.argtypes = [vp, u32, u32]
+    lib.or_memo_warm_lines.restype = u64
+    lib.or_memo_pass_bytes.argtypes = [vp, i32, vp, u64, u32, u32, u32, i32, vp]
+    lib.or_memo_pass_bytes.restype = i32
     lib.or_approx_bounds.argtypes = [u64, u64, vp, u32, u32, vp, vp, vp, vp]
     lib.or_approx_bounds.restype = None
     lib.or_approx_gap_below.argtypes = [u64, u64, vp, u32, u32, u32]
@@ -244,6 +260,69 @@ def walk_cost(g: CSR, starts, wids, L, p, q, seed, d_rule=D_RULE, a_cap=A_CAP, n
     if rc != 0:
         raise ValueError("bad cost arguments")
     return int(b[0]), int(s[0]), int(h[0])
+
+
+def step_cost(g: CSR, seed, wid, s, t, v, p, q, d_rule=D_RULE, a_cap=A_CAP, approx_t=0):
+    """Isolated algorithmic bytes of one move (walk wid, step s, at v after t) and its result."""
+    A = np.array(multipliers(p, q), dtype=np.uint32)
+    nxt = np.zeros(1, dtype=np.uint32)
+    b = _load().or_step_cost(g.handle, seed, wid, s, t, v, _ptr(A), d_rule, a_cap, approx_t, _ptr(nxt))
+    return int(b), int(nxt[0])
+
+
+def walk_cost_classes(g: CSR, starts, wids, L, p, q, seed, d_rule=D_RULE, a_cap=A_CAP, nthreads=None, approx_t=0):
+    """Isolated algorithmic bytes split by class: (bytes, moves) of second-order moves at
+    vertices above d_rule, then (bytes, moves) of every other move."""
+    starts = np.ascontiguousarray(starts, dtype=np.uint32)
+    wids = np.ascontiguousarray(wids, dtype=np.uint64)
+    cls = np.zeros(4, dtype=np.uint64)
+    rc = _load().or_walk_cost_classes(g.handle, _ptr(starts), _ptr(wids), len(starts), L, p, q, seed,
+                                      d_rule, a_cap, approx_t, _ptr(cls), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("bad cost arguments")
+    return tuple(int(x) for x in cls)
+
+
+# memo-aware bytes model of a pass (see oracle.c: or_memo_pass_bytes)
+MEMO_MAX_DEG = 4161536
+
+
+def memo_off_lines(v):
+    return int(_load().or_memo_off_lines(v))
+
+
+def memo_search_levels(d):
+    return int(_load().or_memo_search_levels(d))
+
+
+def memo_pair_lines(off, a, b):
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    return int(_load().or_memo_pair_lines(_ptr(off), a, b))
+
+
+def memo_cold_lines(off, t, v, weighted=False):
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    return int(_load().or_memo_cold_lines(_ptr(off), int(weighted), t, v))
+
+
+def memo_warm_lines(off, t, v):
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    return int(_load().or_memo_warm_lines(_ptr(off), t, v))
+
+
+def memo_pass_bytes(off, out, L, d_rule=D_RULE, memo_min=None, memo=True, weighted=False):
+    """Memo-aware bytes of a pass given by its walk matrix: dict(hub_bytes, hub_moves,
+    other_moves, intersections, warm_moves)."""
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    out = np.ascontiguousarray(out, dtype=np.uint32)
+    res = np.zeros(5, dtype=np.uint64)
+    mm = d_rule + 1 if memo_min is None else memo_min
+    rc = _load().or_memo_pass_bytes(_ptr(off), int(weighted), _ptr(out), out.shape[0], L, d_rule, mm, int(memo),
+                                    _ptr(res))
+    if rc != 0:
+        raise MemoryError("or_memo_pass_bytes")
+    return dict(zip(["hub_bytes", "hub_moves", "other_moves", "intersections", "warm_moves"],
+                    (int(x) for x in res)))
 
 
 def approx_bounds(du, dv, p, q, wlo=1, whi=1):

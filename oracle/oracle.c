@@ -823,13 +823,14 @@ typedef struct {
     uint64_t seed;
     uint32_t d_rule, a_cap, approx_t;
     uint64_t bytes, steps, hub_steps, next;
+    uint64_t hub2_bytes, hub2_steps;  /* second-order moves (s > 0) at vertices above d_rule */
 } or_cost_job;
 
 static void or_cost_task(void *p, int tid, int nth)
 {
     (void)tid; (void)nth;
     or_cost_job *j = (or_cost_job *)p;
-    uint64_t b = 0, st = 0, hs = 0;
+    uint64_t b = 0, st = 0, hs = 0, hb2 = 0, hs2 = 0;
     for (;;) {
         uint64_t i = __atomic_fetch_add(&j->next, 1, __ATOMIC_RELAXED);
         if (i >= j->count) break;
@@ -841,7 +842,9 @@ static void or_cost_task(void *p, int tid, int nth)
             if (x == OR_SENT) break;
             b += c;
             ++st;
-            hs += (j->g->off[v + 1] - j->g->off[v]) > j->d_rule;
+            int hub = (j->g->off[v + 1] - j->g->off[v]) > j->d_rule;
+            hs += hub;
+            if (hub && s > 0) { hb2 += c; ++hs2; }
             t = v;
             v = x;
         }
@@ -849,6 +852,8 @@ static void or_cost_task(void *p, int tid, int nth)
     __atomic_fetch_add(&j->bytes, b, __ATOMIC_RELAXED);
     __atomic_fetch_add(&j->steps, st, __ATOMIC_RELAXED);
     __atomic_fetch_add(&j->hub_steps, hs, __ATOMIC_RELAXED);
+    __atomic_fetch_add(&j->hub2_bytes, hb2, __ATOMIC_RELAXED);
+    __atomic_fetch_add(&j->hub2_steps, hs2, __ATOMIC_RELAXED);
 }
 
 /* Sums the algorithmic bytes, the moves taken and the moves made at        */
@@ -864,5 +869,175 @@ int or_walk_cost(const or_graph *g, const uint32_t *starts, const uint64_t *wids
     j.d_rule = d_rule; j.a_cap = a_cap; j.approx_t = approx_t;
     or_parallel(or_cost_task, &j, nthreads);
     *bytes = j.bytes; *steps = j.steps; *hub_steps = j.hub_steps;
+    return 0;
+}
+
+/* As or_walk_cost, split into two classes: cls[0], cls[1] = bytes and      */
+/* moves of second-order moves (s > 0) at vertices above d_rule (the        */
+/* inverse-CDF class); cls[2], cls[3] = bytes and moves of all other moves. */
+int or_walk_cost_classes(const or_graph *g, const uint32_t *starts, const uint64_t *wids, uint64_t count,
+                         uint32_t L, double p, double q, uint64_t seed, uint32_t d_rule, uint32_t a_cap,
+                         uint32_t approx_t, uint64_t cls[4], int nthreads)
+{
+    or_cost_job j;
+    memset(&j, 0, sizeof j);
+    if (or_multipliers(p, q, j.A) != 0) return -1;
+    j.g = g; j.starts = starts; j.wids = wids; j.count = count; j.L = L; j.seed = seed;
+    j.d_rule = d_rule; j.a_cap = a_cap; j.approx_t = approx_t;
+    or_parallel(or_cost_task, &j, nthreads);
+    cls[0] = j.hub2_bytes;
+    cls[1] = j.hub2_steps;
+    cls[2] = j.bytes - j.hub2_bytes;
+    cls[3] = j.steps - j.hub2_steps;
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Memo-aware algorithmic bytes of a whole pass (the FN-Cache paragraph of */
+/* Section 3.4: work done for popular vertices is kept and reused within  */
+/* a run).  A second-order move at a vertex v above d_rule needs, besides */
+/* v's row bounds and its 4-byte output, either                            */
+/*   - the intersection of N(v) with N(t), when no earlier move of the     */
+/*     pass computed it ("cold"), or                                       */
+/*   - a kept per-pair summary of it ("warm"): 64 segment counts and 64    */
+/*     first-half counts of members of N(t) in equal segments of N(v), and */
+/*     64 start positions in N(t) (192 two-byte words: 6 lines), plus the  */
+/*     half segment of N(v) that holds the drawn prefix sum and the part of */
+/*     N(t) whose values fall in it (its share of N(t) in proportion),     */
+/* whichever is cheaper for the move (the directed cold cost below against */
+/* the warm one).  The intersection behind a summary is charged once per   */
+/* pass and pair whose moves read it: the cheaper of a                     */
+/* streaming merge of both rows and a search of each member of the shorter */
+/* row in the longer (one line per search level below a 16-entry line,    */
+/* at least one), on top of reading the shorter row.  A summary serves     */
+/* both directions of a pair when both endpoints keep summaries (degree in */
+/* [memo_min, 4161536]); otherwise only moves at the endpoint that keeps   */
+/* them.  Moves at vertices that keep none (and every move of a weighted   */
+/* graph, or of a pass without summaries) pay the directed cold cost each  */
+/* time.  The directed cold cost: the cheaper of merging N(v) with N(t) and */
+/* searching N(t)'s                                                         */
+/* members in N(v), plus the weights of N(v) for a weighted graph.  All    */
+/* counts are 64-byte lines of arrays that start on a line.  The pass is   */
+/* given by its walk matrix (count x (L+1), N2V sentinel after the end).   */
+/* ---------------------------------------------------------------------- */
+#define OR_MEMO_MAX_DEG 4161536ull
+
+static uint64_t lines_of(uint64_t elem, uint64_t lo, uint64_t hi)
+{
+    if (hi <= lo) return 0;
+    return ((hi * elem - 1) >> 6) - ((lo * elem) >> 6) + 1;
+}
+
+/* Lines holding off[v] and off[v+1]. */
+uint64_t or_memo_off_lines(uint32_t v)
+{
+    return lines_of(8, v, (uint64_t)v + 2);
+}
+
+/* Search levels charged per member searched in a row of d entries:        */
+/* ceil(log2(d / 16)), at least 1.                                          */
+uint64_t or_memo_search_levels(uint64_t d)
+{
+    uint64_t k = 1;
+    while ((16ull << k) < d) ++k;
+    return k;
+}
+
+/* Lines of one intersection of the rows of a and b (unweighted). */
+uint64_t or_memo_pair_lines(const uint64_t *off, uint32_t a, uint32_t b)
+{
+    uint64_t da = off[a + 1] - off[a], db = off[b + 1] - off[b];
+    uint64_t dense = lines_of(4, off[a], off[a + 1]) + lines_of(4, off[b], off[b + 1]);
+    uint32_t sh = da <= db ? a : b;
+    uint64_t dsh = da <= db ? da : db, dlo = da <= db ? db : da;
+    uint64_t search = lines_of(4, off[sh], off[sh + 1]) + dsh * or_memo_search_levels(dlo);
+    return search < dense ? search : dense;
+}
+
+/* Lines of one move at v after t evaluated without a summary. */
+uint64_t or_memo_cold_lines(const uint64_t *off, int weighted, uint32_t t, uint32_t v)
+{
+    uint64_t dv = off[v + 1] - off[v], dt = off[t + 1] - off[t];
+    uint64_t rt = lines_of(4, off[t], off[t + 1]);
+    uint64_t w = weighted ? lines_of(2, off[v], off[v + 1]) : 0;
+    uint64_t dense = lines_of(4, off[v], off[v + 1]) + rt + w;
+    uint64_t search = rt + dt * or_memo_search_levels(dv) + w;
+    return search < dense ? search : dense;
+}
+
+/* Lines of one move at v after t that reads a summary. */
+uint64_t or_memo_warm_lines(const uint64_t *off, uint32_t t, uint32_t v)
+{
+    uint64_t dv = off[v + 1] - off[v], dt = off[t + 1] - off[t];
+    uint64_t tiles = (dv + 511) / 512;
+    uint64_t seglen = ((tiles + 63) / 64) * 512;
+    uint64_t h = seglen / 2 < dv ? seglen / 2 : dv;
+    uint64_t ht = (dt * h + dv - 1) / dv;
+    return 6 + (4 * h + 63) / 64 + (4 * ht + 63) / 64;
+}
+
+static int or_memo_keeps(uint64_t d, uint32_t memo_min)
+{
+    return d >= memo_min && d <= OR_MEMO_MAX_DEG;
+}
+
+/* Totals over a pass: res[0] = bytes of second-order moves at vertices     */
+/* above d_rule (cold and warm, intersections included), res[1] = those     */
+/* moves, res[2] = all other moves (first moves and moves at vertices of    */
+/* degree <= d_rule), res[3] = intersections charged, res[4] = warm moves.  */
+/* memo = 0 or a weighted graph: no summaries.  Returns -1 on allocation    */
+/* failure.                                                                 */
+int or_memo_pass_bytes(const uint64_t *off, int weighted, const uint32_t *out, uint64_t count, uint32_t L,
+                       uint32_t d_rule, uint32_t memo_min, int memo, uint64_t res[5])
+{
+    uint64_t cap = 1024, nk = 0;
+    uint64_t *keys = (uint64_t *)malloc(cap * sizeof(uint64_t));
+    if (!keys) return -1;
+    memset(res, 0, 5 * sizeof(uint64_t));
+    int summaries = memo && !weighted;
+    for (uint64_t i = 0; i < count; ++i) {
+        const uint32_t *row = out + i * (uint64_t)(L + 1);
+        for (uint32_t s = 0; s < L; ++s) {
+            if (row[s] == OR_SENT || row[s + 1] == OR_SENT) break;
+            uint32_t v = row[s];
+            uint64_t dv = off[v + 1] - off[v];
+            if (s == 0 || dv <= d_rule) { res[2] += 1; continue; }
+            uint32_t t = row[s - 1];
+            res[1] += 1;
+            uint64_t lines = or_memo_off_lines(v);
+            uint64_t cold = or_memo_cold_lines(off, weighted, t, v);
+            uint64_t warm = summaries && or_memo_keeps(dv, memo_min) ? or_memo_warm_lines(off, t, v) : cold;
+            if (warm < cold) {
+                lines += warm;
+                res[4] += 1;
+                uint64_t dt = off[t + 1] - off[t];
+                uint64_t key;
+                if (or_memo_keeps(dt, memo_min))
+                    key = t < v ? ((uint64_t)t << 32) | v : ((uint64_t)v << 32) | t;
+                else
+                    key = ((uint64_t)v << 32) | t;
+                if (nk == cap) {
+                    uint64_t *nkeys = (uint64_t *)realloc(keys, 2 * cap * sizeof(uint64_t));
+                    if (!nkeys) { free(keys); return -1; }
+                    keys = nkeys;
+                    cap *= 2;
+                }
+                keys[nk++] = key;
+            } else {
+                lines += cold;
+            }
+            res[0] += lines * 64 + 4;
+        }
+    }
+    if (nk) {
+        qsort(keys, nk, sizeof(uint64_t), or_cmp_u64);
+        for (uint64_t k = 0; k < nk; ++k) {
+            if (k > 0 && keys[k] == keys[k - 1]) continue;
+            uint32_t a = (uint32_t)(keys[k] >> 32), b = (uint32_t)keys[k];
+            res[0] += or_memo_pair_lines(off, a, b) * 64;
+            res[3] += 1;
+        }
+    }
+    free(keys);
     return 0;
 }

@@ -29,7 +29,7 @@ EXPORTS = [
     "n2v_rmat_workspace", "n2v_rmat_generate",
     "n2v_graph_opts_default", "n2v_graph_workspace", "n2v_graph_create", "n2v_graph_destroy",
     "n2v_graph_info", "n2v_graph_check", "n2v_graph_memo_bytes", "n2v_graph_set_memo",
-    "n2v_graph_memo_plan", "n2v_graph_set_memo_min",
+    "n2v_graph_memo_plan", "n2v_graph_set_memo_min", "n2v_graph_memo_clear",
     "n2v_exec_opts_default", "n2v_walk", "n2v_walk_workspace", "n2v_walk_ex", "n2v_walk_approx",
     "n2v_visit_profile",
     "n2v_autotune_workspace", "n2v_autotune",
@@ -78,7 +78,7 @@ class Result(C.Structure):
                 ("start_ns", C.c_uint64), ("done_ns", C.c_uint64)]
 
 
-ABI_VERSION = 6  # layout of the option structs and sketch rows, entry points
+ABI_VERSION = 7  # layout of the option structs and sketch rows, entry points
 _lib = None
 
 
@@ -108,6 +108,7 @@ def lib():
         "n2v_graph_set_memo": ([vp, vp, sz], i32),
         "n2v_graph_memo_plan": ([vp, sz, P(u32), P(sz)], i32),
         "n2v_graph_set_memo_min": ([vp, vp, sz, u32], i32),
+        "n2v_graph_memo_clear": ([vp, vp], i32),
         "n2v_exec_opts_default": ([vp, P(ExecOpts)], None),
         "n2v_walk": ([vp, vp, u32, u32, f32, f32, u64, vp, vp], i32),
         "n2v_walk_workspace": ([vp, u32, u32, P(ExecOpts), P(sz)], i32),
@@ -255,28 +256,36 @@ class Graph:
     def attach_memo(self, budget=None):
         """Allocates and attaches pair-sketch memory (unweighted graphs); returns its bytes.  With a
         byte budget, only rows of the highest-degree vertices that fit keep sketches (0 if none)."""
+        # the previous memory stays referenced until the library has switched
+        # to the new one (a refused attach leaves the graph on the old memory)
         if budget is None:
             b = C.c_size_t()
             check(lib().n2v_graph_memo_bytes(self._h, C.byref(b)), "n2v_graph_memo_bytes")
             if b.value == 0:
                 return 0
-            self.memo = _alloc(b.value, self.device)
-            check(lib().n2v_graph_set_memo(self._h, _ptr(self.memo), self.memo.numel()), "n2v_graph_set_memo")
+            mem = _alloc(b.value, self.device)
+            check(lib().n2v_graph_set_memo(self._h, _ptr(mem), mem.numel()), "n2v_graph_set_memo")
+            self.memo = mem
             self.memo_min_degree = self.d_rule + 1
             return b.value
         dmin, b = C.c_uint32(), C.c_size_t()
         check(lib().n2v_graph_memo_plan(self._h, int(budget), C.byref(dmin), C.byref(b)), "n2v_graph_memo_plan")
         if b.value == 0:
             return 0
-        self.memo = _alloc(b.value, self.device)
-        check(lib().n2v_graph_set_memo_min(self._h, _ptr(self.memo), self.memo.numel(), dmin.value),
-              "n2v_graph_set_memo_min")
+        mem = _alloc(b.value, self.device)
+        check(lib().n2v_graph_set_memo_min(self._h, _ptr(mem), mem.numel(), dmin.value), "n2v_graph_set_memo_min")
+        self.memo = mem
         self.memo_min_degree = dmin.value
         return b.value
+
+    def memo_clear(self, stream=None):
+        """Enqueues the clearing of the pair sketches: the next walk pass starts cold."""
+        check(lib().n2v_graph_memo_clear(self._h, _stream(stream)), "n2v_graph_memo_clear")
 
     def detach_memo(self):
         check(lib().n2v_graph_set_memo(self._h, None, 0), "n2v_graph_set_memo")
         self.memo = None
+        self.memo_min_degree = None
 
     def check_starts(self, stream=None):
         check(lib().n2v_graph_check(self._h, _stream(stream)), "n2v_graph_check")

@@ -33,6 +33,10 @@ constexpr int CURSOR_STRIDE = 64;  // words between counters (one per 256 bytes)
 int set_error(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 
+// Host bookkeeping of a graph's walk-counter slots (walk.hip).
+void *cursor_slots_new();
+void cursor_slots_free(void *slots);
+
 #define N2V_HIP(call)                                              \
     do {                                                           \
         hipError_t e_ = (call);                                    \
@@ -231,6 +235,9 @@ struct n2v_graph {
     uint64_t hub_entries;   // entries in rows of degree > d_rule
     uint64_t memo_entries;  // entries in rows of degree >= dg.memo_min (sketch rows)
     void *scan;             // scan scratch of the graph's workspace
-    uint32_t next_cursor;   // round-robin counter slot
+    unsigned long long *hist;  // 64 words of the graph's workspace for degree statistics
+    uint32_t next_cursor;   // next walk-counter slot to try
     size_t memo_bytes;      // attached sketch memory (0: none)
+    int servers;            // servers created on this graph and not yet destroyed
+    void *slots;            // walk-counter slot bookkeeping (host; see walk.hip)
 };

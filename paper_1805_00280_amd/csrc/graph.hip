@@ -153,6 +153,7 @@ struct GraphLayout {
     uint64_t *wsum;
     uint64_t *hbase;
     void *scan;
+    unsigned long long *hist;
     uint32_t *status;
     uint32_t *cursors;
 };
@@ -167,6 +168,7 @@ size_t graph_layout(uint32_t n, uint64_t m, int weighted, void *ws, size_t ws_by
     L->wsum = weighted ? c.take<uint64_t>((uint64_t)n + 1) : nullptr;
     L->hbase = c.take<uint64_t>((uint64_t)n + 1);
     L->scan = c.take<char>(scan_scratch_bytes((uint64_t)n + 1));
+    L->hist = c.take<unsigned long long>(64);
     return c.total();
 }
 
@@ -254,6 +256,13 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
     N2V_HIP(hipStreamSynchronize(st));
     n2v_graph *g = (n2v_graph *)calloc(1, sizeof(n2v_graph));
     if (!g) return set_error(N2V_ENOMEM, "n2v_graph_create: host allocation failed");
+    g->slots = cursor_slots_new();
+    if (!g->slots) {
+        free(g);
+        return set_error(N2V_ENOMEM, "n2v_graph_create: host allocation failed");
+    }
+    g->hist = L.hist;
+    g->servers = 0;
     g->dg.hbase = L.hbase;
     g->dg.memo = nullptr;
     g->hub_entries = hub_entries;
@@ -290,6 +299,10 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
 
 extern "C" int n2v_graph_destroy(n2v_graph *g)
 {
+    if (!g) return N2V_OK;
+    if (__atomic_load_n(&g->servers, __ATOMIC_ACQUIRE) > 0)
+        return set_error(N2V_EINVAL, "n2v_graph_destroy: %d server(s) still use this graph", g->servers);
+    cursor_slots_free(g->slots);
     free(g);
     return N2V_OK;
 }
@@ -313,6 +326,29 @@ extern "C" int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes)
     return N2V_OK;
 }
 
+namespace {
+
+__global__ void k_zero_u64w(unsigned long long *p, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// Entries in rows of degree >= dmin, through the graph's statistics words
+// (synchronous on the default stream).
+unsigned long long deg_sum_ge(const n2v_graph *g, uint64_t dmin, int *rc)
+{
+    unsigned long long e = 0;
+    *rc = N2V_OK;
+    hipLaunchKernelGGL(k_zero_u64w, dim3(1), dim3(64), 0, 0, g->hist, 1u);
+    hipLaunchKernelGGL(k_deg_sum_ge, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin, g->hist);
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) err = hipMemcpy(&e, g->hist, sizeof(e), hipMemcpyDeviceToHost);
+    if (err != hipSuccess) *rc = hip_fail(err, "degree sum");
+    return e;
+}
+
+}  // namespace
+
 extern "C" int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *min_degree, size_t *bytes)
 {
     if (!g || !min_degree || !bytes) return set_error(N2V_EINVAL, "n2v_graph_memo_plan: null argument");
@@ -324,20 +360,14 @@ extern "C" int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *
         *bytes = g->hub_entries * row;
         return N2V_OK;
     }
-    unsigned long long *hist = nullptr;
-    N2V_HIP(hipMalloc(&hist, 64 * sizeof(unsigned long long)));
+    // degree statistics go through 64 words of the graph's own workspace
+    unsigned long long *hist = g->hist;
     unsigned long long h[64];
+    hipLaunchKernelGGL(k_zero_u64w, dim3(1), dim3(64), 0, 0, hist, 64u);
+    hipLaunchKernelGGL(k_deg_hist, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin, hist);
+    N2V_HIP(hipGetLastError());
+    N2V_HIP(hipMemcpy(h, hist, sizeof(h), hipMemcpyDeviceToHost));
     int rc = N2V_OK;
-    if (hipMemset(hist, 0, sizeof(h)) != hipSuccess) rc = hip_fail(hipGetLastError(), "hipMemset");
-    if (!rc) {
-        hipLaunchKernelGGL(k_deg_hist, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin, hist);
-        if (hipMemcpy(h, hist, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
-            rc = hip_fail(hipGetLastError(), "hipMemcpy");
-    }
-    if (rc) {
-        (void)hipFree(hist);
-        return rc;
-    }
     // the first power of two above d_rule whose rows fit brackets the answer:
     // the threshold below it (half of it, or d_rule + 1) does not fit
     uint64_t lo = 0, hi = 0, hi_e = 0;
@@ -356,16 +386,8 @@ extern "C" int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *
     // over one-pass sums of the degrees at or above a candidate
     while (!rc && hi && hi - lo > 1) {
         const uint64_t mid = lo + (hi - lo) / 2;
-        unsigned long long e = 0;
-        if (hipMemset(hist, 0, sizeof(unsigned long long)) != hipSuccess) {
-            rc = hip_fail(hipGetLastError(), "hipMemset");
-            break;
-        }
-        hipLaunchKernelGGL(k_deg_sum_ge, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, mid, hist);
-        if (hipMemcpy(&e, hist, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess) {
-            rc = hip_fail(hipGetLastError(), "hipMemcpy");
-            break;
-        }
+        const unsigned long long e = deg_sum_ge(g, mid, &rc);
+        if (rc) break;
         if (e * row <= budget) {
             hi = mid;
             hi_e = e;
@@ -373,7 +395,6 @@ extern "C" int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *
             lo = mid;
         }
     }
-    (void)hipFree(hist);
     if (rc) return rc;
     if (hi && hi <= 0xFFFFFFFFull) {
         *min_degree = (uint32_t)hi;
@@ -385,9 +406,31 @@ extern "C" int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *
     return N2V_OK;
 }
 
+namespace {
+
+__global__ void k_clear_words(uint32_t *p, uint64_t n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+int clear_memo(void *mem, size_t bytes, hipStream_t st)
+{
+    const uint64_t words = (uint64_t)bytes / 4;
+    if (words == 0) return N2V_OK;
+    hipLaunchKernelGGL(k_clear_words, dim3((uint32_t)std::min<uint64_t>((words + 255) / 256, 65536)), dim3(256), 0,
+                       st, (uint32_t *)mem, words);
+    N2V_HIP(hipGetLastError());
+    return N2V_OK;
+}
+
+}  // namespace
+
 extern "C" int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uint32_t min_degree)
 {
     if (!g) return set_error(N2V_EINVAL, "n2v_graph_set_memo_min: null graph");
+    if (__atomic_load_n(&g->servers, __ATOMIC_ACQUIRE) > 0)
+        return set_error(N2V_EINVAL, "n2v_graph_set_memo: %d server(s) use this graph's sketches", g->servers);
     if (!mem) {
         g->dg.memo = nullptr;
         g->memo_bytes = 0;
@@ -396,26 +439,43 @@ extern "C" int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uin
     if (g->weighted) return set_error(N2V_EINVAL, "n2v_graph_set_memo: weighted graphs keep no pair sketches");
     if (((uintptr_t)mem & 255) != 0) return set_error(N2V_EINVAL, "n2v_graph_set_memo: memory not 256-byte aligned");
     const uint64_t dmin = std::max<uint64_t>(min_degree, (uint64_t)g->dg.d_rule + 1);
-    if (dmin != g->dg.memo_min) {  // re-index the sketch rows for the new threshold
+    // the rows the threshold keeps are counted before anything changes, so a
+    // refusal leaves the handle exactly as it was
+    uint64_t rows = g->memo_entries;
+    if (dmin != g->dg.memo_min) {
+        int rc = N2V_OK;
+        rows = deg_sum_ge(g, dmin, &rc);
+        if (rc) return rc;
+    }
+    const size_t need = (size_t)rows * MEMO_ROW * sizeof(uint16_t);
+    if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
+    // detached while the rows are re-indexed: a failure below leaves no
+    // memory attached rather than memory indexed for another threshold
+    g->dg.memo = nullptr;
+    g->memo_bytes = 0;
+    if (dmin != g->dg.memo_min) {
         hipLaunchKernelGGL(k_hub_len, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin,
                            (uint64_t *)g->dg.hbase);
         N2V_HIP(hipGetLastError());
         int rc = exclusive_scan_u64((uint64_t *)g->dg.hbase, (uint64_t)g->dg.n + 1, g->scan, 0);
         if (rc) return rc;
-        uint64_t e = 0;
-        N2V_HIP(hipMemcpy(&e, g->dg.hbase + g->dg.n, sizeof(uint64_t), hipMemcpyDeviceToHost));
-        g->memo_entries = e;
+        g->memo_entries = rows;
         g->dg.memo_min = (uint32_t)std::min<uint64_t>(dmin, 0xFFFFFFFFull);
     }
-    const size_t need = (size_t)g->memo_entries * MEMO_ROW * sizeof(uint16_t);
-    if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
-    // all entries start unknown: servers read sketches without a walk call
-    // having cleared them first
-    N2V_HIP(hipMemset(mem, 0, bytes));
+    // every entry starts unknown
+    int rc = clear_memo(mem, bytes, 0);
+    if (rc) return rc;
     N2V_HIP(hipDeviceSynchronize());
     g->dg.memo = (uint16_t *)mem;
     g->memo_bytes = bytes;
     return N2V_OK;
+}
+
+extern "C" int n2v_graph_memo_clear(n2v_graph *g, void *stream)
+{
+    if (!g) return set_error(N2V_EINVAL, "n2v_graph_memo_clear: null graph");
+    if (!g->dg.memo) return N2V_OK;
+    return clear_memo(g->dg.memo, g->memo_bytes, (hipStream_t)stream);
 }
 
 extern "C" int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes)

@@ -359,6 +359,9 @@ extern "C" int n2v_server_create(const n2v_graph *g, void *pool, size_t pool_byt
     if (pool_bytes < reserve + 4096) return set_error(N2V_ENOMEM, "n2v_server_create: pool too small");
     n2v_server *s = new n2v_server();
     s->g = g;
+    // the graph's sketch memory and rows stay fixed while a server replays
+    // ticks captured with them (attaching returns N2V_EINVAL meanwhile)
+    __atomic_fetch_add(&const_cast<n2v_graph *>(g)->servers, 1, __ATOMIC_ACQ_REL);
     n2v_server_opts_default(&s->o);
     if (opts) s->o = *opts;
     if (s->o.chunk_walks < 1) s->o.chunk_walks = 1;
@@ -371,6 +374,7 @@ extern "C" int n2v_server_create(const n2v_graph *g, void *pool, size_t pool_byt
     if (s->own_stream) {
         hipError_t e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking);
         if (e != hipSuccess) {
+            __atomic_fetch_sub(&const_cast<n2v_graph *>(g)->servers, 1, __ATOMIC_ACQ_REL);
             delete s;
             return hip_fail(e, "hipStreamCreateWithFlags");
         }
@@ -438,6 +442,7 @@ extern "C" int n2v_server_destroy(n2v_server *s)
         if (t.host) (void)hipHostFree(t.host);
     }
     if (s->own_stream) (void)hipStreamDestroy(s->st);
+    __atomic_fetch_sub(&const_cast<n2v_graph *>(s->g)->servers, 1, __ATOMIC_ACQ_REL);
     delete s;
     return N2V_OK;
 }

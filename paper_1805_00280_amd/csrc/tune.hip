@@ -78,21 +78,35 @@ extern "C" int n2v_autotune(n2v_graph *g, uint32_t n_walks, uint32_t L, float p,
     c.A_out = A_out;
     c.approx_t = 0;
 
-    hipEvent_t e0, e1;
-    N2V_HIP(hipEventCreate(&e0));
-    N2V_HIP(hipEventCreate(&e1));
+    // events released on every return path
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    N2V_HIP(hipEventCreate(&ev.a));
+    N2V_HIP(hipEventCreate(&ev.b));
+    // Each candidate is timed from cold pair sketches, as a fresh pass over a
+    // graph meets them: the sketches are cleared before its warm-up launch and
+    // again before its timed launch, so no candidate reuses merges that the
+    // warm-up or an earlier candidate made on the same sample.
     auto run = [&](const n2v_exec_opts &o, double *ms) -> int {
         Exec E;
         make_exec(g, o, &E);
-        int rc = launch_one(E, c, T.starts, n_walks, o, g->device, st);  // warm-up
+        int rc = n2v_graph_memo_clear(g, st);
+        if (!rc) rc = launch_one(g, E, c, T.starts, n_walks, o, st);  // warm-up
+        if (!rc) rc = n2v_graph_memo_clear(g, st);
         if (rc) return rc;
-        N2V_HIP(hipEventRecord(e0, st));
-        rc = launch_one(E, c, T.starts, n_walks, o, g->device, st);
+        N2V_HIP(hipEventRecord(ev.a, st));
+        rc = launch_one(g, E, c, T.starts, n_walks, o, st);
         if (rc) return rc;
-        N2V_HIP(hipEventRecord(e1, st));
-        N2V_HIP(hipEventSynchronize(e1));
+        N2V_HIP(hipEventRecord(ev.b, st));
+        N2V_HIP(hipEventSynchronize(ev.b));
         float f = 0;
-        N2V_HIP(hipEventElapsedTime(&f, e0, e1));
+        N2V_HIP(hipEventElapsedTime(&f, ev.a, ev.b));
         *ms = f;
         return N2V_OK;
     };
@@ -126,8 +140,9 @@ extern "C" int n2v_autotune(n2v_graph *g, uint32_t n_walks, uint32_t L, float p,
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // leave the sketches cold for the caller's next pass
+    rc = n2v_graph_memo_clear(g, st);
+    if (rc) return rc;
     cur.mode = N2V_MODE_AUTO;
     g->tuned = cur;
     g->has_tuned = true;

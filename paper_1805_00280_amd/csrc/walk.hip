@@ -25,6 +25,8 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <mutex>
+#include <new>
 
 #include "prims.hpp"
 #include "walk.hpp"
@@ -1753,11 +1755,53 @@ int walk_multipliers(float p, float q, uint32_t *A_ret, uint32_t *A_out)
     return 0;
 }
 
+// Walk counters of a graph: a persistent launch takes a counter slot that no
+// launch still in flight holds (an event recorded after each launch tells),
+// so overlapping calls never share a counter.
+struct CursorSlots {
+    std::mutex mu;
+    hipEvent_t ev[CURSOR_SLOTS] = {};
+    int next = 0;
+};
+
+void *cursor_slots_new() { return new (std::nothrow) CursorSlots(); }
+
+void cursor_slots_free(void *p)
+{
+    CursorSlots *cs = (CursorSlots *)p;
+    if (!cs) return;
+    for (hipEvent_t &e : cs->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete cs;
+}
+
+template <class F>
+int with_cursor(const n2v_graph *g, hipStream_t st, F launch)
+{
+    CursorSlots *cs = (CursorSlots *)g->slots;
+    std::lock_guard<std::mutex> lk(cs->mu);
+    int slot = -1;
+    for (int k = 0; k < CURSOR_SLOTS && slot < 0; ++k) {
+        const int i = (cs->next + k) % CURSOR_SLOTS;
+        if (!cs->ev[i]) N2V_HIP(hipEventCreateWithFlags(&cs->ev[i], hipEventDisableTiming));
+        const hipError_t q = hipEventQuery(cs->ev[i]);
+        if (q == hipSuccess) slot = i;
+        else if (q != hipErrorNotReady) return hip_fail(q, "hipEventQuery (walk counter)");
+    }
+    if (slot < 0)
+        return set_error(N2V_EAGAIN, "n2v_walk: %d persistent walk calls on this graph are still in flight",
+                         CURSOR_SLOTS);
+    cs->next = (slot + 1) % CURSOR_SLOTS;
+    const int rc = launch(g->dg.cursors + (uint64_t)slot * CURSOR_STRIDE);
+    if (rc) return rc;
+    N2V_HIP(hipEventRecord(cs->ev[slot], st));
+    return N2V_OK;
+}
+
 void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E)
 {
     E->g = g->dg;
-    const uint32_t slot = __atomic_fetch_add(&const_cast<n2v_graph *>(g)->next_cursor, 1u, __ATOMIC_RELAXED);
-    E->cursor = g->dg.cursors + (uint64_t)(slot % CURSOR_SLOTS) * CURSOR_STRIDE;
+    E->cursor = nullptr;  // persistent launches take one per launch (with_cursor)
     if (!o.memo) E->g.memo = nullptr;
     E->t_wave = o.t_wave;
     E->t_sparse = o.t_sparse;
@@ -1781,15 +1825,17 @@ int launch_job_table(const Exec &E, const TableHdr *hdr, uint32_t blocks, hipStr
     return N2V_OK;
 }
 
-int launch_one(const Exec &E, const JobCtx &c, const uint32_t *starts, uint32_t n, const n2v_exec_opts &o, int dev,
-               hipStream_t st)
+int launch_one(const n2v_graph *g, const Exec &E, const JobCtx &c, const uint32_t *starts, uint32_t n,
+               const n2v_exec_opts &o, hipStream_t st)
 {
     OneJob S;
     S.c = c;
     S.starts = starts;
     S.n = n;
-    S.cur = E.cursor;
-    return launch_persistent<true, false>(E, S, o, dev, st);
+    return with_cursor(g, st, [&](uint32_t *cur) {
+        S.cur = cur;
+        return launch_persistent<true, false>(E, S, o, g->device, st);
+    });
 }
 
 }  // namespace n2v
@@ -1863,14 +1909,8 @@ extern "C" int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint3
     S.c.approx_t = approx_t;
     S.starts = starts;
     S.n = n_starts;
-    S.cur = E.cursor;
+    S.cur = nullptr;
     hipStream_t st = (hipStream_t)stream;
-    if (E.g.memo) {  // sketches are rebuilt within each call
-        const uint64_t words = (uint64_t)g->memo_bytes / 4;
-        hipLaunchKernelGGL(k_zero64, dim3((uint32_t)std::min<uint64_t>((words + 255) / 256, 65536)), dim3(256), 0, st,
-                           (uint32_t *)E.g.memo, words);
-        N2V_HIP(hipGetLastError());
-    }
 
     if (o.mode == N2V_MODE_PLAIN) {
         const size_t need = plain_ws(n_starts, L);
@@ -1880,9 +1920,12 @@ extern "C" int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint3
         if (W) return launch_plain<true, false>(E, S, ws, g->device, st);
         return launch_plain<false, true>(E, S, ws, g->device, st);
     }
-    if (W && C) return launch_persistent<true, true>(E, S, o, g->device, st);
-    if (W) return launch_persistent<true, false>(E, S, o, g->device, st);
-    return launch_persistent<false, true>(E, S, o, g->device, st);
+    return with_cursor(g, st, [&](uint32_t *cur) {
+        S.cur = cur;
+        if (W && C) return launch_persistent<true, true>(E, S, o, g->device, st);
+        if (W) return launch_persistent<true, false>(E, S, o, g->device, st);
+        return launch_persistent<false, true>(E, S, o, g->device, st);
+    });
 }
 
 extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,

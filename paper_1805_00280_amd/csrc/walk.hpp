@@ -15,7 +15,7 @@ struct Exec {
     uint32_t sparse_ratio;  // cost weight of one search against streaming
     uint32_t t_wg;          // plain form: dense hub moves at degree > t_wg use a whole workgroup
     uint32_t search_ratio;  // dense merges search N(v) in N(t) when N(t)'s range is longer by more
-    uint32_t *cursor;       // next unassigned walk of a single-job launch (zeroed before it)
+    uint32_t *cursor;       // walk counter of a single-job launch (taken per launch, zeroed before it)
 };
 
 // Parameters of one walk job: a set of walks with the same (L, p, q, seed).
@@ -53,7 +53,8 @@ int walk_multipliers(float p, float q, uint32_t *A_ret, uint32_t *A_out);
 void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E);
 uint32_t full_grid_blocks(int dev);
 int launch_job_table(const Exec &E, const TableHdr *hdr, uint32_t blocks, hipStream_t st);
-int launch_one(const Exec &E, const JobCtx &c, const uint32_t *starts, uint32_t n, const n2v_exec_opts &o, int dev,
-               hipStream_t st);
+// One persistent launch of a single job on the graph's walk counters.
+int launch_one(const n2v_graph *g, const Exec &E, const JobCtx &c, const uint32_t *starts, uint32_t n,
+               const n2v_exec_opts &o, hipStream_t st);
 
 }  // namespace n2v

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.n2v_abi_version() == 6
+    assert lib.n2v_abi_version() == 7
 
 
 def test_defaults(lib):
@@ -83,6 +83,7 @@ def test_memo_calls_reject_null_arguments(lib):
     assert lib.n2v_graph_memo_plan(None, 0, C.byref(dmin), C.byref(b)) == -1
     assert lib.n2v_graph_set_memo_min(None, None, 0, 0) == -1
     assert lib.n2v_graph_memo_bytes(None, C.byref(b)) == -1
+    assert lib.n2v_graph_memo_clear(None, None) == -1
 
 
 def test_visit_profile_and_approx_reject_null_arguments(lib):

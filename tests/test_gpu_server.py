@@ -166,3 +166,38 @@ def test_server_with_pair_sketches_from_garbage_memory():
     srv.close()
     assert P.lib().n2v_graph_set_memo(g._h, None, 0) == 0
     del buf
+
+
+def test_live_server_blocks_memo_changes_and_destroy():
+    # while a server holds the graph, attaching or detaching sketch memory and destroying the
+    # graph return N2V_EINVAL and change nothing; after the server is gone all three work
+    import ctypes as C
+    import torch
+    torch_cuda()
+    og = oracle_rmat(12, 16, 0.65, 0.15, 0.15, 3, False)
+    g = gpu_graph_from_oracle(og, d_rule=40)
+    g.attach_memo()
+    memo_before = g.memo
+    srv = P.Server(g, pool_bytes=32 << 20, chunk_walks=512, max_inflight=4)
+    b = C.c_size_t()
+    assert P.lib().n2v_graph_memo_bytes(g._h, C.byref(b)) == 0
+    other = torch.zeros(b.value, dtype=torch.uint8, device="cuda")
+    assert P.lib().n2v_graph_set_memo(g._h, C.c_void_p(other.data_ptr()), b.value) == -1
+    assert b"server" in P.lib().n2v_last_error()
+    assert P.lib().n2v_graph_set_memo(g._h, None, 0) == -1
+    assert P.lib().n2v_graph_set_memo_min(g._h, C.c_void_p(other.data_ptr()), b.value, 100) == -1
+    assert P.lib().n2v_graph_destroy(g._h) == -1
+    with pytest.raises(P.N2VError) as e:
+        g.attach_memo()
+    assert e.value.code == -1 and g.memo is memo_before
+    starts = np.arange(0, og.n, 3, dtype=np.uint32)
+    t = srv.submit(starts, 15, 0.5, 2.0, 21)
+    done = wait_all(srv, [t])
+    want = O.walk(og, starts, 15, 0.5, 2.0, 21, d_rule=40, nthreads=16)["out"]
+    assert np.array_equal(srv.result_tensor(done[t]), want)
+    srv.release(t)
+    srv.close()
+    assert P.lib().n2v_graph_set_memo(g._h, C.c_void_p(other.data_ptr()), b.value) == 0
+    assert P.lib().n2v_graph_set_memo(g._h, None, 0) == 0
+    g.close()
+    del other

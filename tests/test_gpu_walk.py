@@ -487,3 +487,61 @@ def test_uniform_weights_walk_like_unweighted():
             assert first_mismatch(b, a) is None, (mode, T, first_mismatch(b, a))
             want = oracle_walk(og, starts, 20, 0.5, 2.0, 9, d_rule=64, approx_t=T)
             assert first_mismatch(a, want) is None, (mode, T, first_mismatch(a, want))
+
+
+def test_memo_min_refusal_leaves_the_graph_unchanged():
+    # too few bytes for a lower threshold: N2V_ENOMEM, and the graph keeps its rows and
+    # memory, so the next walks (which read sketches indexed by those rows) equal the oracle's
+    import ctypes as C
+    import torch
+    torch_cuda()
+    og = oracle_rmat(13, 16, *SKEW, 13, False)
+    g = gpu_graph_from_oracle(og, d_rule=40)
+    deg = og.degree()
+    full = g.attach_memo()
+    g.detach_memo()
+    part = g.attach_memo(budget=full // 4)
+    T = g.memo_min_degree
+    assert part > 0 and T > 41
+    # ask for every hub row (threshold 41) with only the partial size
+    small = torch.zeros(part, dtype=torch.uint8, device="cuda")
+    rc = P.lib().n2v_graph_set_memo_min(g._h, C.c_void_p(small.data_ptr()), part, 41)
+    assert rc == -2, rc
+    hubs = np.argsort(deg)[-128:].astype(np.uint32)
+    starts = np.concatenate([np.repeat(hubs, 8), np.arange(og.n, dtype=np.uint32)])
+    say(f"[walk] refused re-index (threshold {T} kept)")
+    got = gpu_walk(g, starts, 20, 0.25, 4.0, 9)
+    want = oracle_walk(og, starts, 20, 0.25, 4.0, 9, d_rule=40)
+    assert first_mismatch(got, want) is None, first_mismatch(got, want)
+    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192), T)
+    assert n > 50
+    g.detach_memo()
+    del small
+
+
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+def test_sketches_persist_across_calls_and_clear(mode):
+    # sketches describe the graph only: a second call with other (p, q, seed) reuses what the
+    # first filled and still equals the oracle; after n2v_graph_memo_clear every entry is unknown
+    import torch
+    torch_cuda()
+    og = oracle_rmat(13, 16, *SKEW, 17, False)
+    g = gpu_graph_from_oracle(og, d_rule=40)
+    g.attach_memo()
+    deg = og.degree()
+    hubs = np.argsort(deg)[-128:].astype(np.uint32)
+    starts = np.concatenate([np.repeat(hubs, 8), np.arange(og.n, dtype=np.uint32)])
+    say(f"[walk] persisting sketches mode={mode}")
+    for p, q, seed in [(0.25, 4.0, 1), (2.0, 0.5, 2), (1.0, 1.0, 3)]:
+        got = gpu_walk(g, starts, 20, p, q, seed, mode=mode)
+        want = oracle_walk(og, starts, 20, p, q, seed, d_rule=40)
+        assert first_mismatch(got, want) is None, (p, q, first_mismatch(got, want))
+    memo = g.memo.cpu().numpy().view(np.uint16)
+    assert np.count_nonzero(memo) > 0
+    assert check_sketch_rows(og, memo.reshape(-1, 192), 41) > 100
+    g.memo_clear()
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(g.memo).item()) == 0
+    got = gpu_walk(g, starts, 20, 0.5, 2.0, 4, mode=mode)
+    assert first_mismatch(got, oracle_walk(og, starts, 20, 0.5, 2.0, 4, d_rule=40)) is None
+    g.detach_memo()

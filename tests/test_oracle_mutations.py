@@ -48,10 +48,42 @@ MUTATIONS = [
     ("FN-Approx: draw from the second-order law",
      "if (s > 0 && or_approx_applies(g, t, v, A, d_rule, approx_t)) return or_static_draw(g, seed, wid, s, v);",
      "if (s > 0 && or_approx_applies(g, t, v, A, d_rule, approx_t)) return or_inverse_cdf(g, seed, wid, s, 0, t, v, A);"),
+    # the isolated algorithmic-bytes model
+    ("cost: off[v+1] not charged",
+     "    seg_add(&S, SEG_OFF, (uint64_t)v * 8 + 8);", "    (void)0;"),
+    ("cost: merge branch drops N(t)",
+     "    if (s > 0) seg_add_range(&D, SEG_ADJ, ot * 4, (ot + dt) * 4);",
+     "    if (s > 99) seg_add_range(&D, SEG_ADJ, ot * 4, (ot + dt) * 4);"),
+    ("cost: search probes not charged",
+     "        seg_add(s, SEG_ADJ, mid * 4);", "        (void)mid;"),
+    ("cost: sparse branch searches the wrong row",
+     "            uint64_t pos = seg_search(&P, g->adj, ov, ov + d, y);",
+     "            uint64_t pos = seg_search(&P, g->adj, ot, ot + dt, y);"),
+    ("cost: FN-Approx move charged as exact",
+     "    if (s > 0 && or_approx_applies(g, t, v, A, d_rule, approx_t)) {\n        /* first-order draw",
+     "    if (s > 99 && or_approx_applies(g, t, v, A, d_rule, approx_t)) {\n        /* first-order draw"),
+    ("cost: weight of a proposal not charged",
+     "if (g->wt) { seg_add(&S, SEG_WT, (ov + j) * 2); w = g->wt[ov + j]; }", "if (g->wt) { w = g->wt[ov + j]; }"),
+    # the checksum hash
+    ("checksum: column and vertex counter words swapped",
+     "ph(seed, wid, col, x, 3, r);", "ph(seed, wid, x, col, 3, r);"),
+    # the memo-aware model
+    ("memo: summary row not charged",
+     "return 6 + (4 * h + 63) / 64 + (4 * ht + 63) / 64;", "return (4 * h + 63) / 64 + (4 * ht + 63) / 64;"),
+    ("memo: one summary per direction of a pair",
+     "key = t < v ? ((uint64_t)t << 32) | v : ((uint64_t)v << 32) | t;", "key = ((uint64_t)v << 32) | t;"),
+    ("memo: intersection charged on every move",
+     "if (k > 0 && keys[k] == keys[k - 1]) continue;", "if (0) continue;"),
+    ("memo: line of off[v+1] dropped",
+     "return lines_of(8, v, (uint64_t)v + 2);", "return lines_of(8, v, (uint64_t)v + 1);"),
+    ("memo: search levels off by one",
+     "while ((16ull << k) < d) ++k;", "while ((16ull << k) <= d) ++k;"),
+    ("memo: summary read even when dearer",
+     "            if (warm < cold) {", "            if (warm < cold + 1000000) {"),
 ]
 
 TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_rmat.py", "tests/test_oracle_law.py",
-         "tests/test_oracle_invariants.py", "tests/test_oracle_approx.py"]
+         "tests/test_oracle_invariants.py", "tests/test_oracle_approx.py", "tests/test_oracle_cost.py"]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
