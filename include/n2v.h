@@ -274,6 +274,60 @@ int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uint32_t min_d
 int n2v_graph_check(const n2v_graph *g, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Skip-gram with negative sampling over walks (Section 1 and Section 2.1:
+ * node2vec learns vertex embeddings by running Skip-gram over its walks).
+ * One step over a batch of walks (rows of row_len entries, N2V_SENT after a
+ * walk's end) against embedding tables win and wout (device, n x dim fp32,
+ * row-major):
+ *   - each position i < len of a walk (len = entries before the first
+ *     sentinel, row_len <= 96) is a center v = win[x_i]; its contexts are the
+ *     positions j < len with 1 <= |i - j| <= window, u = wout[x_j]; the walk's
+ *     `negatives` (<= 64) vertices n_k, drawn from the noise distribution, are
+ *     negatives of every center of the walk, u = wout[n_k];
+ *   - z = v . u; loss = sum over (center, context) of softplus(-z) + neg_weight
+ *     x sum over (center, negative) of softplus(z), accumulated into *loss
+ *     (device f64);
+ *   - gradients: (sigmoid(z) - 1) u and neg_weight sigmoid(z) u into the
+ *     center's row, (sigmoid(z) - 1) v and neg_weight sigmoid(z) v into the
+ *     target's, summed over the batch;
+ *   - then win -= lr x its gradient and wout -= lr x its gradient (every walk
+ *     of the batch sees the tables as they were before the step).
+ * Products run in bf16 with fp32 accumulation; gradients accumulate in fp32
+ * (atomically, so their summation order varies).
+ * Negative k of the walk with id w (= walk_base + index in the batch):
+ * r = hi64(R1, cum[n]) with R1 = r0*2^32 + r1 of Philox(key = seed;
+ * ctr = (w mod 2^32, k, step, 6)), and the vertex x with cum[x] <= r <
+ * cum[x+1]; cum (device, n+1 u64) is the caller's cumulative noise weight
+ * table (cum[0] = 0, non-decreasing, cum[n] > 0).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint32_t dim;        /* embedding dimension: 128 */
+    uint32_t window;     /* context positions j with 1 <= |i - j| <= window */
+    uint32_t negatives;  /* shared negatives per walk, <= 64 */
+    float neg_weight;    /* weight of each (center, negative) term */
+    float lr;            /* SGD step size */
+    uint64_t seed;       /* negative-sampling key */
+    uint32_t step;       /* step index in the negative-sampling counter */
+} n2v_sgns_params;
+
+/* Workspace bytes of n2v_sgns_step: two n x dim fp32 gradient tables, which
+ * must be zero before the first step (every step leaves them zero), and the
+ * batch's negatives. */
+int n2v_sgns_workspace(uint32_t n, uint32_t dim, uint32_t n_walks, uint32_t negatives, size_t *ws_bytes);
+
+/* The negatives of walks walk_base .. walk_base + n_walks - 1 into out
+ * (device, n_walks x negatives u32), as n2v_sgns_step draws them. */
+int n2v_sgns_negatives(const uint64_t *cum, uint32_t n, uint64_t seed, uint64_t walk_base, uint32_t step,
+                       uint32_t n_walks, uint32_t negatives, uint32_t *out, void *stream);
+
+/* One training step (above).  Errors: N2V_EINVAL (dim != 128, row_len not in
+ * 1..96, negatives > 64, misaligned workspace or tables), N2V_ENOMEM
+ * (workspace smaller than the query).  Asynchronous on `stream`. */
+int n2v_sgns_step(const n2v_sgns_params *prm, const uint32_t *walks, uint32_t n_walks, uint32_t row_len,
+                  uint64_t walk_base, const uint64_t *cum, uint32_t n, float *win, float *wout, void *ws,
+                  size_t ws_bytes, double *loss, void *stream);
+
+/* ------------------------------------------------------------------------
  * Autotuner: times the persistent kernel on a seeded sample of walks from
  * the graph under a set of candidate execution options and stores the best
  * in the graph (n2v_exec_opts_default then returns it).  Outputs are

@@ -1041,3 +1041,25 @@ int or_memo_pass_bytes(const uint64_t *off, int weighted, const uint32_t *out, u
     free(keys);
     return 0;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Skip-gram negatives (the stage that consumes the walks, Sections 1 and */
+/* 2.1): negative k of walk w at training step `step` is the vertex x with */
+/* cum[x] <= r < cum[x+1], r = hi64(R1, cum[n]), R1 = r0*2^32 + r1 of      */
+/* Philox(key = seed; ctr = (w mod 2^32, k, step, 6)).  cum is the         */
+/* cumulative noise weight table (cum[0] = 0, cum[n] > 0).                 */
+/* ---------------------------------------------------------------------- */
+void or_sgns_negatives(const uint64_t *cum, uint32_t n, uint64_t seed, uint64_t walk_base, uint32_t step,
+                       uint32_t n_walks, uint32_t nneg, uint32_t *out)
+{
+    for (uint64_t i = 0; i < n_walks; ++i) {
+        for (uint32_t k = 0; k < nneg; ++k) {
+            uint32_t r[4];
+            ph(seed, (uint32_t)(walk_base + i), k, step, 6, r);
+            uint64_t target = hi64(((uint64_t)r[0] << 32) | r[1], cum[n]);
+            uint32_t x = 0;
+            while (!(cum[x] <= target && target < cum[x + 1])) ++x; /* linear scan: plain */
+            out[i * nneg + k] = x;
+        }
+    }
+}

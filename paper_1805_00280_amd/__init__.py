@@ -32,6 +32,7 @@ EXPORTS = [
     "n2v_graph_memo_plan", "n2v_graph_set_memo_min", "n2v_graph_memo_clear",
     "n2v_exec_opts_default", "n2v_walk", "n2v_walk_workspace", "n2v_walk_ex", "n2v_walk_approx",
     "n2v_visit_profile",
+    "n2v_sgns_workspace", "n2v_sgns_negatives", "n2v_sgns_step",
     "n2v_autotune_workspace", "n2v_autotune",
     "n2v_server_opts_default", "n2v_server_create", "n2v_server_destroy", "n2v_submit", "n2v_poll",
     "n2v_release", "n2v_server_stats",
@@ -71,6 +72,11 @@ class ServerOpts(C.Structure):
 class Request(C.Structure):
     _fields_ = [("host_starts", C.c_void_p), ("n_starts", C.c_uint32), ("L", C.c_uint32), ("p", C.c_float),
                 ("q", C.c_float), ("seed", C.c_uint64), ("approx_t", C.c_uint32)]
+
+
+class SgnsParams(C.Structure):
+    _fields_ = [("dim", C.c_uint32), ("window", C.c_uint32), ("negatives", C.c_uint32), ("neg_weight", C.c_float),
+                ("lr", C.c_float), ("seed", C.c_uint64), ("step", C.c_uint32)]
 
 
 class Result(C.Structure):
@@ -116,6 +122,9 @@ def lib():
         "n2v_walk_approx": ([vp, vp, u32, u64, u32, f32, f32, u64, u32, P(ExecOpts), i32, vp, vp, vp, vp, sz, vp],
                             i32),
         "n2v_visit_profile": ([vp, vp, u32, u32, vp, vp, vp], i32),
+        "n2v_sgns_workspace": ([u32, u32, u32, u32, P(sz)], i32),
+        "n2v_sgns_negatives": ([vp, u32, u64, u64, u32, u32, u32, vp, vp], i32),
+        "n2v_sgns_step": ([P(SgnsParams), vp, u32, u32, u64, vp, u32, vp, vp, vp, sz, vp, vp], i32),
         "n2v_autotune_workspace": ([vp, u32, u32, P(sz)], i32),
         "n2v_autotune": ([vp, u32, u32, f32, f32, vp, sz, vp, P(ExecOpts), P(C.c_double)], i32),
         "n2v_server_opts_default": ([P(ServerOpts)], None),
@@ -361,6 +370,47 @@ class Graph:
         check(lib().n2v_autotune(self._h, n_walks, L, p, q, _ptr(work), work.numel(), _stream(stream),
                                  C.byref(best), C.byref(ms)), "n2v_autotune")
         return best, ms.value
+
+
+# --------------------------------------------------------------------------
+class SkipGram:
+    """Skip-gram with negative sampling over walks (n2v_sgns_step): embedding tables
+    win and wout (n x 128 fp32, device) trained in steps over batches of walk rows."""
+
+    DIM = 128
+
+    def __init__(self, n, win, wout, cum, window=10, negatives=64, neg_weight=None, lr=0.025, seed=1,
+                 max_walks=1 << 16, device="cuda"):
+        torch = _torch()
+        self.n, self.win, self.wout, self.device = n, win, wout, device
+        self.cum = cum  # device u64 (int64 tensor) cumulative noise weights, n + 1
+        k = 5 * 2 * window  # word2vec's 5 negatives per (center, context) pair, spread over the shared ones
+        self.prm = SgnsParams(self.DIM, window, negatives, neg_weight if neg_weight is not None else k / negatives,
+                              lr, seed, 0)
+        ws = C.c_size_t()
+        check(lib().n2v_sgns_workspace(n, self.DIM, max_walks, negatives, C.byref(ws)), "n2v_sgns_workspace")
+        self.ws = torch.zeros(max(ws.value, 256), dtype=torch.uint8, device=device)
+        self.max_walks = max_walks
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def step(self, walks, walk_base=0, step=None, stream=None):
+        """One SGD step over walk rows (int32 tensor view of uint32, n_walks x row_len)."""
+        n_walks, row_len = int(walks.shape[0]), int(walks.shape[1])
+        if n_walks > self.max_walks:
+            raise ValueError(f"batch of {n_walks} walks exceeds the workspace's {self.max_walks}")
+        if step is not None:
+            self.prm.step = step
+        check(lib().n2v_sgns_step(C.byref(self.prm), _ptr(walks), n_walks, row_len, walk_base, _ptr(self.cum), self.n,
+                                  _ptr(self.win), _ptr(self.wout), _ptr(self.ws), self.ws.numel(), _ptr(self.loss),
+                                  _stream(stream)), "n2v_sgns_step")
+        self.prm.step += 1
+
+    def negatives(self, n_walks, walk_base=0, step=0, stream=None):
+        torch = _torch()
+        out = torch.empty((n_walks, self.prm.negatives), dtype=torch.int32, device=self.device)
+        check(lib().n2v_sgns_negatives(_ptr(self.cum), self.n, self.prm.seed, walk_base, step, n_walks,
+                                       self.prm.negatives, _ptr(out), _stream(stream)), "n2v_sgns_negatives")
+        return out
 
 
 # --------------------------------------------------------------------------

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libn2v.so")
-SOURCES = ["api.hip", "prims.hip", "rmat.hip", "graph.hip", "walk.hip", "tune.hip", "server.hip"]
+SOURCES = ["api.hip", "prims.hip", "rmat.hip", "graph.hip", "walk.hip", "tune.hip", "server.hip", "skipgram.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

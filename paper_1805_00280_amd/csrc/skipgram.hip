@@ -1,0 +1,342 @@
+// skipgram.hip -- Skip-gram with negative sampling over node2vec walks.
+//
+// The walks feed a Skip-gram model (Section 1 and Section 2.1 of the paper:
+// node2vec learns embeddings by running Skip-gram over its random walks).
+// One training step over a batch of walks, every walk with its own set of
+// shared negatives:
+//   - centers: the walk's vertices x_0 .. x_{len-1} (len = entries before the
+//     first sentinel); context of position i: positions j with
+//     1 <= |i - j| <= window; negatives: the walk's `negatives` vertices drawn
+//     from the noise distribution;
+//   - z = v(center) . u(context or negative), v rows of `win`, u rows of `wout`;
+//   - loss: softplus(-z) per (center, context) pair plus neg_weight *
+//     softplus(z) per (center, negative) pair;
+//   - gradient coefficients g = sigmoid(z) - 1 (context) and
+//     neg_weight * sigmoid(z) (negative); dv = sum g u, du = sum g v;
+//   - after every walk of the batch is evaluated against the same tables, both
+//     tables take one SGD step: w -= lr * gradient.
+// Per walk the three contractions (logits, center gradients, target
+// gradients) are dense products of at most 96 centers by 160 targets by 128
+// dimensions; one workgroup evaluates them with bf16 MFMA (fp32 accumulate)
+// from LDS tiles, and adds the gradient rows into fp32 gradient tables.
+#include <math.h>
+
+#include <algorithm>
+
+#include "prims.hpp"
+
+namespace n2v {
+
+namespace {
+
+constexpr int SG_DIM = 128;               // embedding dimension
+constexpr int SG_MAXC = 96;               // walk positions per walk (L + 1 <= 96)
+constexpr int SG_MAXNEG = 64;             // shared negatives per walk
+constexpr int SG_T = SG_MAXC + SG_MAXNEG; // targets: walk positions, then negatives
+constexpr int SG_BLOCK = 256;             // four wavefronts
+// LDS row strides (bf16 elements), padded against bank conflicts
+constexpr int LD_V = SG_DIM + 8;    // V[c][d], T[t][d]
+constexpr int LD_VT = SG_MAXC + 8;  // Vt[d][c], Gt[t][c]
+constexpr int LD_TT = SG_T + 8;     // Tt[d][t], G[c][t]
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct SgArgs {
+    const uint32_t *walks;   // n_walks x row_len
+    const uint32_t *negs;    // n_walks x nneg
+    const float *win, *wout; // n x SG_DIM
+    float *gin, *gout;       // n x SG_DIM gradient accumulators
+    double *loss;
+    uint32_t n_walks, row_len, nneg, window;
+    float neg_weight;
+};
+
+// Row-major LDS tiles of one walk (139 KB; 16-byte aligned rows for the
+// operand loads).  After the logits, G and Gt take the place of V and T.
+struct alignas(16) SgLds {
+    union {
+        struct {
+            __bf16 V[SG_MAXC * LD_V];
+            __bf16 T[SG_T * LD_V];
+        } in;
+        struct {
+            __bf16 G[SG_MAXC * LD_TT];
+            __bf16 Gt[SG_T * LD_VT];
+        } g;
+    } u;
+    __bf16 Vt[SG_DIM * LD_VT];
+    __bf16 Tt[SG_DIM * LD_TT];
+    uint32_t ids[SG_T];
+    float wloss[SG_BLOCK / WAVE];
+};
+
+__device__ __forceinline__ bf16x8 lds8(const __bf16 *p) { return *(const bf16x8 *)p; }
+
+// One 32x32 output tile: sum over k < K of A[ra + i][k] * B[cb + j][k], with A
+// and B row-major in LDS (row strides lda, ldb).  Lane l supplies row l % 32 of
+// A and of B, k-slices 8 (l / 32) .. +8 of each 16-wide step.
+template <int K>
+__device__ __forceinline__ f32x16 tile_dot(const __bf16 *A, int lda, int ra, const __bf16 *B, int ldb, int cb)
+{
+    const int l = lane_id();
+    const __bf16 *a = A + (ra + (l & 31)) * lda + 8 * (l >> 5);
+    const __bf16 *b = B + (cb + (l & 31)) * ldb + 8 * (l >> 5);
+    f32x16 acc = {};
+#pragma unroll
+    for (int k = 0; k < K; k += 16) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lds8(a + k), lds8(b + k), acc, 0, 0, 0);
+    return acc;
+}
+
+// Row of accumulator register r of lane l within a 32x32 tile (its column is l % 32).
+__device__ __forceinline__ int tile_row(int r) { return 8 * (r >> 2) + 4 * (lane_id() >> 5) + (r & 3); }
+
+__device__ __forceinline__ float softplus(float x) { return x > 0.f ? x + log1pf(expf(-x)) : log1pf(expf(x)); }
+
+__device__ __forceinline__ float sigmoid(float x) { return 1.f / (1.f + expf(-x)); }
+
+__global__ __launch_bounds__(SG_BLOCK, 1) void k_sg_walks(SgArgs A)
+{
+    __shared__ SgLds S;
+    const int tid = threadIdx.x, l = lane_id(), wv = tid / WAVE;
+    const uint32_t walk = blockIdx.x;
+    const uint32_t *row = A.walks + (uint64_t)walk * A.row_len;
+    // positions before the first sentinel
+    if (tid < SG_T) {
+        uint32_t id = SENT;
+        if (tid < SG_MAXC) id = (uint32_t)tid < A.row_len ? row[tid] : SENT;
+        else if ((uint32_t)(tid - SG_MAXC) < A.nneg) id = A.negs[(uint64_t)walk * A.nneg + (tid - SG_MAXC)];
+        S.ids[tid] = id;
+    }
+    __syncthreads();
+    uint32_t len = 0;
+    while (len < A.row_len && S.ids[len] != SENT) ++len;
+    // rows to bf16 tiles, row-major and transposed: 32 lanes per row, 4 floats each
+    for (int r = tid / 32; r < SG_MAXC + SG_T; r += SG_BLOCK / 32) {
+        const int q = tid & 31;
+        const bool center = r < SG_MAXC;
+        const int t = center ? r : r - SG_MAXC;
+        const uint32_t id = S.ids[t];
+        const bool valid = center ? (uint32_t)r < len : (t < SG_MAXC ? (uint32_t)t < len : (uint32_t)(t - SG_MAXC) < A.nneg);
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (valid) x = *(const float4 *)((center ? A.win : A.wout) + (uint64_t)id * SG_DIM + 4 * q);
+        const __bf16 b0 = (__bf16)x.x, b1 = (__bf16)x.y, b2 = (__bf16)x.z, b3 = (__bf16)x.w;
+        __bf16 *dst = center ? S.u.in.V + t * LD_V : S.u.in.T + t * LD_V;
+        dst[4 * q] = b0;
+        dst[4 * q + 1] = b1;
+        dst[4 * q + 2] = b2;
+        dst[4 * q + 3] = b3;
+        __bf16 *tr = center ? S.Vt + t : S.Tt + t;
+        const int ld = center ? LD_VT : LD_TT;
+        tr[(4 * q) * ld] = b0;
+        tr[(4 * q + 1) * ld] = b1;
+        tr[(4 * q + 2) * ld] = b2;
+        tr[(4 * q + 3) * ld] = b3;
+    }
+    __syncthreads();
+    // logits: 3 x 5 tiles of 32 x 32, tile k of this wave is wv + 4k; gradient
+    // coefficients and the loss are formed in the accumulators
+    f32x16 gz[4];
+    float loss = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int tile = wv + 4 * k;
+        if (tile < 15) {
+            const int ti = tile / 5, tj = tile % 5;
+            f32x16 z = tile_dot<SG_DIM>(S.u.in.V, LD_V, 32 * ti, S.u.in.T, LD_V, 32 * tj);
+            const uint32_t t = 32 * tj + (l & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t c = 32 * ti + tile_row(r);
+                float g = 0.f;
+                if (c < len) {
+                    if (t < (uint32_t)SG_MAXC) {
+                        const uint32_t dist = c > t ? c - t : t - c;
+                        if (t < len && dist >= 1 && dist <= A.window) {
+                            g = sigmoid(z[r]) - 1.f;
+                            loss += softplus(-z[r]);
+                        }
+                    } else if (t - SG_MAXC < A.nneg) {
+                        g = A.neg_weight * sigmoid(z[r]);
+                        loss += A.neg_weight * softplus(z[r]);
+                    }
+                }
+                z[r] = g;
+            }
+            gz[k] = z;
+        }
+    }
+    __syncthreads();  // V and T are read for the last time above
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int tile = wv + 4 * k;
+        if (tile < 15) {
+            const int ti = tile / 5, tj = tile % 5;
+            const int t = 32 * tj + (l & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int c = 32 * ti + tile_row(r);
+                const __bf16 g = (__bf16)gz[k][r];
+                S.u.g.G[c * LD_TT + t] = g;
+                S.u.g.Gt[t * LD_VT + c] = g;
+            }
+        }
+    }
+    // loss of the workgroup
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) loss += __shfl_xor(loss, m, WAVE);
+    if (l == 0) S.wloss[wv] = loss;
+    __syncthreads();
+    if (tid == 0) {
+        const float s = S.wloss[0] + S.wloss[1] + S.wloss[2] + S.wloss[3];
+        if (s != 0.f) atomicAdd(A.loss, (double)s);
+    }
+    // center gradients dV = G T: 3 x 4 tiles, added into the input-side table
+    for (int tile = wv; tile < 12; tile += 4) {
+        const int ti = tile / 4, tj = tile % 4;
+        const f32x16 acc = tile_dot<SG_T>(S.u.g.G, LD_TT, 32 * ti, S.Tt, LD_TT, 32 * tj);
+        const int d = 32 * tj + (l & 31);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t c = 32 * ti + tile_row(r);
+            if (c < len) atomicAdd(A.gin + (uint64_t)S.ids[c] * SG_DIM + d, acc[r]);
+        }
+    }
+    // target gradients dT = Gt V: 5 x 4 tiles, added into the output-side table
+    for (int tile = wv; tile < 20; tile += 4) {
+        const int ti = tile / 4, tj = tile % 4;
+        const f32x16 acc = tile_dot<SG_MAXC>(S.u.g.Gt, LD_VT, 32 * ti, S.Vt, LD_VT, 32 * tj);
+        const int d = 32 * tj + (l & 31);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t t = 32 * ti + tile_row(r);
+            const bool valid = t < (uint32_t)SG_MAXC ? t < len : t - SG_MAXC < A.nneg;
+            if (valid) atomicAdd(A.gout + (uint64_t)S.ids[t] * SG_DIM + d, acc[r]);
+        }
+    }
+}
+
+// w -= lr * g and g = 0 over a table (count floats, a multiple of 4).
+__global__ __launch_bounds__(256) void k_sg_apply(float *__restrict__ w, float *__restrict__ g, uint64_t count4,
+                                                  float lr)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count4; i += stride) {
+        float4 a = ((float4 *)w)[i];
+        const float4 b = ((float4 *)g)[i];
+        a.x -= lr * b.x;
+        a.y -= lr * b.y;
+        a.z -= lr * b.z;
+        a.w -= lr * b.w;
+        ((float4 *)w)[i] = a;
+        ((float4 *)g)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// Negative k of walk i: r = hi64(R1, total) with R1 from Philox(seed; (walk
+// id, k, step, 6)); the vertex x with cum[x] <= r < cum[x+1].
+__global__ __launch_bounds__(256) void k_sg_negatives(const uint64_t *__restrict__ cum, uint32_t n, uint32_t k0,
+                                                      uint32_t k1, uint32_t wbase, uint32_t step, uint32_t n_walks,
+                                                      uint32_t nneg, uint32_t *__restrict__ out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)n_walks * nneg) return;
+    const uint32_t w = (uint32_t)(i / nneg), k = (uint32_t)(i % nneg);
+    const R4 r = philox(k0, k1, wbase + w, k, step, 6u);
+    const uint64_t target = hi64(join64(r.x, r.y), cum[n]);
+    uint32_t lo = 0, hi = n;  // first x with cum[x + 1] > target
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (cum[mid + 1] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    out[i] = lo;
+}
+
+struct SgLayout {
+    float *gin, *gout;
+    uint32_t *negs;
+};
+
+size_t sg_layout(uint32_t n, uint32_t n_walks, uint32_t nneg, void *ws, size_t ws_bytes, SgLayout *L)
+{
+    Carver c(ws, ws_bytes);
+    L->gin = c.take<float>((uint64_t)n * SG_DIM);
+    L->gout = c.take<float>((uint64_t)n * SG_DIM);
+    L->negs = c.take<uint32_t>((uint64_t)(n_walks ? n_walks : 1) * (nneg ? nneg : 1));
+    return c.total();
+}
+
+}  // namespace
+
+}  // namespace n2v
+
+using namespace n2v;
+
+extern "C" int n2v_sgns_workspace(uint32_t n, uint32_t dim, uint32_t n_walks, uint32_t negatives, size_t *ws_bytes)
+{
+    if (!ws_bytes || n == 0) return set_error(N2V_EINVAL, "n2v_sgns_workspace: bad argument");
+    if (dim != SG_DIM) return set_error(N2V_EINVAL, "n2v_sgns_workspace: dim must be %d", SG_DIM);
+    SgLayout L;
+    *ws_bytes = sg_layout(n, n_walks, negatives, nullptr, 0, &L);
+    return N2V_OK;
+}
+
+extern "C" int n2v_sgns_negatives(const uint64_t *cum, uint32_t n, uint64_t seed, uint64_t walk_base, uint32_t step,
+                                  uint32_t n_walks, uint32_t negatives, uint32_t *out, void *stream)
+{
+    if (!cum || !out || n == 0) return set_error(N2V_EINVAL, "n2v_sgns_negatives: bad argument");
+    if (walk_base + (uint64_t)n_walks > (1ull << 32)) return set_error(N2V_EINVAL, "n2v_sgns_negatives: walk ids exceed 2^32");
+    const uint64_t count = (uint64_t)n_walks * negatives;
+    if (count == 0) return N2V_OK;
+    if (count > 0xFFFFFFFFull * 256) return set_error(N2V_EINVAL, "n2v_sgns_negatives: too many draws");
+    hipLaunchKernelGGL(k_sg_negatives, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, (hipStream_t)stream, cum,
+                       n, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)walk_base, step, n_walks, negatives, out);
+    N2V_HIP(hipGetLastError());
+    return N2V_OK;
+}
+
+extern "C" int n2v_sgns_step(const n2v_sgns_params *prm, const uint32_t *walks, uint32_t n_walks, uint32_t row_len,
+                             uint64_t walk_base, const uint64_t *cum, uint32_t n, float *win, float *wout, void *ws,
+                             size_t ws_bytes, double *loss, void *stream)
+{
+    if (!prm || !walks || !cum || !win || !wout || !ws || !loss || n == 0)
+        return set_error(N2V_EINVAL, "n2v_sgns_step: null argument");
+    if (prm->dim != SG_DIM) return set_error(N2V_EINVAL, "n2v_sgns_step: dim must be %d", SG_DIM);
+    if (row_len < 1 || row_len > (uint32_t)SG_MAXC)
+        return set_error(N2V_EINVAL, "n2v_sgns_step: rows of 1 .. %d entries (walks of at most %d moves)", SG_MAXC,
+                         SG_MAXC - 1);
+    if (prm->negatives > (uint32_t)SG_MAXNEG)
+        return set_error(N2V_EINVAL, "n2v_sgns_step: at most %d negatives per walk", SG_MAXNEG);
+    if (n_walks >= 0x80000000u) return set_error(N2V_EINVAL, "n2v_sgns_step: at most 2^31-1 walks per step");
+    if (((uintptr_t)ws & 255) != 0 || ((uintptr_t)win & 15) != 0 || ((uintptr_t)wout & 15) != 0)
+        return set_error(N2V_EINVAL, "n2v_sgns_step: workspace must be 256-byte and tables 16-byte aligned");
+    SgLayout L;
+    const size_t need = sg_layout(n, n_walks, prm->negatives, ws, ws_bytes, &L);
+    if (need > ws_bytes) return set_error(N2V_ENOMEM, "n2v_sgns_step: workspace %zu < %zu bytes", ws_bytes, need);
+    if (n_walks == 0) return N2V_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = n2v_sgns_negatives(cum, n, prm->seed, walk_base, prm->step, n_walks, prm->negatives, L.negs, stream);
+    if (rc) return rc;
+    SgArgs A;
+    A.walks = walks;
+    A.negs = L.negs;
+    A.win = win;
+    A.wout = wout;
+    A.gin = L.gin;
+    A.gout = L.gout;
+    A.loss = loss;
+    A.n_walks = n_walks;
+    A.row_len = row_len;
+    A.nneg = prm->negatives;
+    A.window = prm->window;
+    A.neg_weight = prm->neg_weight;
+    hipLaunchKernelGGL(k_sg_walks, dim3(n_walks), dim3(SG_BLOCK), 0, st, A);
+    N2V_HIP(hipGetLastError());
+    const uint64_t count4 = (uint64_t)n * SG_DIM / 4;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((count4 + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_sg_apply, dim3(blocks), dim3(256), 0, st, win, L.gin, count4, prm->lr);
+    hipLaunchKernelGGL(k_sg_apply, dim3(blocks), dim3(256), 0, st, wout, L.gout, count4, prm->lr);
+    N2V_HIP(hipGetLastError());
+    return N2V_OK;
+}

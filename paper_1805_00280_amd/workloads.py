@@ -127,24 +127,63 @@ PAPER_TABLE1 = {
 PAPER_FN_BASE_SECONDS = {"skew1.78": 314.5, "skew2": 369.3, "skew3": 811.1, "skew4": 1710.4, "skew5": 2913.4}
 
 
-def serving_requests(count: int, n: int, seed: int = 4, max_log2: int = 20):
-    """Request stream of the serving workload: sizes log-uniform in [1, 2^max_log2],
-    L uniform in {20, 40, 80}, p and q uniform over {0.25, 0.5, 1, 2, 4}, starts
-    uniform over the vertices, one seed per request."""
-    rng = np.random.default_rng(seed)
-    pq = np.array([0.25, 0.5, 1.0, 2.0, 4.0])
-    out = []
-    for j in range(count):
-        size = int(np.floor(2.0 ** (max_log2 * rng.random())))
+def philox_np(k0: int, k1: int, c0, c1, c2, c3):
+    """Philox4x32-10 (Salmon et al., SC'11) over numpy arrays of counter words,
+    for drawing inputs (request streams); returns four uint32 arrays."""
+    c0, c1, c2, c3 = (np.asarray(c, dtype=np.uint64) & 0xFFFFFFFF for c in (c0, c1, c2, c3))
+    c0, c1, c2, c3 = np.broadcast_arrays(c0, c1, c2, c3)
+    k0, k1 = np.uint64(k0 & 0xFFFFFFFF), np.uint64(k1 & 0xFFFFFFFF)
+    m32 = np.uint64(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = np.uint64(0xD2511F53) * c0
+        p1 = np.uint64(0xCD9E8D57) * c2
+        c0, c1, c2, c3 = (p1 >> np.uint64(32)) ^ c1 ^ k0, p1 & m32, (p0 >> np.uint64(32)) ^ c3 ^ k1, p0 & m32
+        k0 = (k0 + np.uint64(0x9E3779B9)) & m32
+        k1 = (k1 + np.uint64(0xBB67AE85)) & m32
+    return tuple(x.astype(np.uint32) for x in (c0, c1, c2, c3))
+
+
+SERVING_PQ = (0.25, 0.5, 1.0, 2.0, 4.0)
+SERVING_L = (20, 40, 80)
+
+
+def serving_request(j: int, n: int, master: int = 4, size: int | None = None, max_log2: int = 20):
+    """Request j of the serving stream, drawn from Philox with key = master and
+    counters tagged 4: size floor(2^(max_log2 U)) in [1, 2^max_log2] (or `size`),
+    L uniform over {20, 40, 80}, p and q uniform over {1/4, 1/2, 1, 2, 4}, starts
+    uniform over [0, n), its own 63-bit seed and a uniform U for its arrival gap."""
+    k0, k1 = master & 0xFFFFFFFF, master >> 32
+    r = [int(x) for x in philox_np(k0, k1, j, 0, 0, 4)]
+    if size is None:
+        size = int(np.floor(2.0 ** (max_log2 * (r[0] / 2.0**32))))
         size = max(1, min(size, 1 << max_log2))
-        out.append({
-            "starts": rng.integers(0, n, size=size, dtype=np.uint64).astype(np.uint32),
-            "L": int(rng.choice([20, 40, 80])),
-            "p": float(rng.choice(pq)),
-            "q": float(rng.choice(pq)),
-            "seed": int(rng.integers(0, 2**63)),
-        })
+    L = SERVING_L[(r[1] * 3) >> 32]
+    p = SERVING_PQ[(r[2] * 5) >> 32]
+    q = SERVING_PQ[(r[3] * 5) >> 32]
+    s = [int(x) for x in philox_np(k0, k1, j, 1, 0, 4)]
+    seed = ((s[0] << 32) | s[1]) >> 1
+    gap_u = (s[2] + 0.5) / 2.0**32
+    i = np.arange(size, dtype=np.uint64)
+    words = philox_np(k0, k1, j, 2, i >> np.uint64(2), 4)
+    w = np.choose((i & np.uint64(3)).astype(np.int64), words).astype(np.uint64)
+    starts = ((w * np.uint64(n)) >> np.uint64(32)).astype(np.uint32)
+    return {"starts": starts, "L": L, "p": p, "q": q, "seed": seed, "gap_u": gap_u}
+
+
+def serving_requests(count: int, n: int, first: int = 0, master: int = 4, max_log2: int = 20):
+    """Requests first .. first+count-1 of the Philox-drawn serving stream."""
+    return [serving_request(j, n, master, max_log2=max_log2) for j in range(first, first + count)]
+
+
+def arrival_times(reqs, rate: float):
+    """Poisson arrivals at `rate` requests per second: exponential gaps from each
+    request's own uniform draw."""
+    t, out = 0.0, []
+    for r in reqs:
+        t += -np.log(1.0 - r["gap_u"]) / rate
+        out.append(t)
     return out
+
 
 # FN-Approx speedup over FN-Base at the ends of the skew study (Section 4.6).
 PAPER_FN_APPROX_SPEEDUP = {("skew1.78", 0.5, 2.0): 1.45, ("skew5", 0.5, 2.0): 17.2,

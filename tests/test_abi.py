@@ -99,7 +99,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     pairs = [("n2v_rmat_params", P.RmatParams), ("n2v_graph_opts", P.GraphOpts), ("n2v_exec_opts", P.ExecOpts),
-             ("n2v_server_opts", P.ServerOpts), ("n2v_request", P.Request), ("n2v_result", P.Result)]
+             ("n2v_server_opts", P.ServerOpts), ("n2v_request", P.Request), ("n2v_result", P.Result),
+             ("n2v_sgns_params", P.SgnsParams)]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "n2v.h"', "int main(void) {"]
     for cname, cls in pairs:
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -47,12 +47,14 @@ def _run(w, sample, attach_memo, approx_t=0):
 
 @pytest.mark.timeout(600)
 def test_scale20_weighted_workload():
-    assert _run(WL.C2, 2048, False) > 0
+    # 2^16 seeded-random walks of the 10.5M against the oracle, every row plain == persistent
+    assert _run(WL.C2, 1 << 16, False) > 0
 
 
 @pytest.mark.timeout(900)
 def test_scale24_skewed_workload():
-    assert _run(WL.C3, 256, True) > 0
+    # 2^16 seeded-random walks of the 67.1M against the oracle, every row plain == persistent
+    assert _run(WL.C3, 1 << 16, True) > 0
 
 
 @pytest.mark.timeout(900)
@@ -105,3 +107,55 @@ def test_counts_workload_shape(mode):
     torch.cuda.synchronize()
     assert np.array_equal(u32(cnt), ref["cnt"])
     assert int(cs.cpu().numpy().view(np.uint64)[0]) == ref["checksum"]
+
+
+@pytest.mark.timeout(1200)
+def test_scale27_counts_workload():
+    # the counts workload at its own size: 4.2G directed entries (u64 offsets, rows past entry
+    # 2^31), device CSR byte-equal to the oracle's; then the top 2^16 walk ids of the 2^27
+    # (walk_base 2^27 - 2^16, counter words at the top of the 32-bit range) against the oracle:
+    # visit counts, checksum and rows, with pair sketches on the highest-degree rows
+    torch = torch_cuda()
+    w = WL.C5
+    say(f"[c5] {w.name}: device graph")
+    g = P.Graph.from_rmat(*w.rmat_args(), weighted=False, device="cuda")
+    # 2^32 directed keys generated, 4.22G entries after de-duplication: offsets past 2^31
+    assert (1 << 31) < g.m < (1 << 32)
+    memo = g.attach_memo(budget=24 << 30)
+    say(f"[c5] m={g.m}, sketches {memo / 2**30:.1f} GiB for rows of degree >= {g.memo_min_degree}")
+    say(f"[c5] oracle graph")
+    og = O.rmat_csr(*w.rmat_args(), weighted=False, nthreads=16)
+    assert og.m == g.m
+    assert np.array_equal(g.off.cpu().numpy().view(np.uint64), og.off)
+    step = 1 << 28
+    for lo in range(0, og.m, step):
+        hi = min(lo + step, og.m)
+        assert np.array_equal(u32(g.adj[lo:hi]), og.adj[lo:hi]), (lo, hi)
+    say(f"[c5] CSR byte-equal")
+    k = 1 << 16
+    base = w.walks - k
+    st = torch.arange(base, w.walks, dtype=torch.int64, device="cuda").remainder_(w.n).to(torch.int32)
+    cnt = torch.zeros(w.n, dtype=torch.int32, device="cuda")
+    cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = torch.empty((k, w.L + 1), dtype=torch.int32, device="cuda")
+    say(f"[c5] walks [{base}, {w.walks}) on the device")
+    g.walk_counts(st, w.L, w.p, w.q, w.seed, cnt, cs, walk_base=base, out=out)
+    torch.cuda.synchronize()
+    g.check_starts()
+    say(f"[c5] oracle on the same walks")
+    ref = O.walk(og, (np.arange(base, w.walks, dtype=np.uint64) % w.n).astype(np.uint32), w.L, w.p, w.q, w.seed,
+                 walk_base=base, want_counts=True, nthreads=16)
+    got = u32(out)
+    assert first_mismatch(got, ref["out"]) is None, first_mismatch(got, ref["out"])
+    assert np.array_equal(u32(cnt), ref["cnt"])
+    assert int(cs.cpu().numpy().view(np.uint64)[0]) == ref["checksum"]
+    say(f"[c5] {ref['transitions']} moves: rows, counts and checksum equal the oracle's")
+    # a mid-range chunk reaches more of the graph (its starts have edges more often)
+    base2, k2 = (1 << 26) + 12345, 4096
+    st2 = torch.arange(base2, base2 + k2, dtype=torch.int32, device="cuda")
+    out2 = g.walk(st2, w.L, w.p, w.q, w.seed, walk_base=base2)
+    torch.cuda.synchronize()
+    ref2 = O.walk(og, np.arange(base2, base2 + k2, dtype=np.uint32), w.L, w.p, w.q, w.seed, walk_base=base2,
+                  nthreads=16)
+    assert first_mismatch(u32(out2), ref2["out"]) is None, first_mismatch(u32(out2), ref2["out"])
+    say(f"[c5] mid-range chunk: {ref2['transitions']} moves equal the oracle's")

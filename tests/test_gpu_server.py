@@ -201,3 +201,41 @@ def test_live_server_blocks_memo_changes_and_destroy():
     assert P.lib().n2v_graph_set_memo(g._h, None, 0) == 0
     g.close()
     del other
+
+
+@pytest.mark.timeout(900)
+def test_serving_workload_at_size():
+    # the serving workload as the bench runs it: the R-MAT scale-22 graph resident with pair
+    # sketches, a 24 GiB pool, 65536-walk chunks, 64 chunks and 2^19 walks per tick, and a
+    # Philox-drawn request set that includes two 2^20-walk requests, all submitted together.
+    # Every result equals the same request walked alone, and the oracle on sampled rows (all
+    # rows of requests up to 2048 walks)
+    import torch
+    from paper_1805_00280_amd import workloads as WL
+    from gpuhelp import u32
+    torch_cuda()
+    w = WL.C4
+    g = P.Graph.from_rmat(*w.rmat_args(), weighted=False, device="cuda")
+    g.attach_memo()
+    og = oracle_rmat(*w.rmat_args(), False)
+    assert np.array_equal(u32(g.adj), og.adj)
+    reqs = [WL.serving_request(j, w.n) for j in range(14)]
+    reqs += [WL.serving_request(100, w.n, size=1 << 20), WL.serving_request(101, w.n, size=1 << 20)]
+    say(f"[c4] sizes {[len(r['starts']) for r in reqs]}")
+    srv = P.Server(g, pool_bytes=24 << 30, chunk_walks=65536, max_inflight=64, tick_walks=1 << 19)
+    tickets = [srv.submit(r["starts"], r["L"], r["p"], r["q"], r["seed"]) for r in reqs]
+    done = wait_all(srv, tickets, timeout=300)
+    rng = np.random.default_rng(9)
+    for r, t in zip(reqs, tickets):
+        got = srv.result_tensor(done[t])
+        srv.release(t)
+        n = len(r["starts"])
+        alone = gpu_walk(g, r["starts"], r["L"], r["p"], r["q"], r["seed"])
+        assert np.array_equal(got, alone), f"request of {n} walks differs from the same request alone"
+        idx = np.arange(n) if n <= 2048 else np.sort(rng.choice(n, size=1024, replace=False))
+        want = O.walk(og, r["starts"][idx], r["L"], r["p"], r["q"], r["seed"], wids=idx.astype(np.uint64),
+                      nthreads=16)["out"]
+        assert np.array_equal(got[idx], want), f"request of {n} walks differs from the oracle"
+    say(f"[c4] {len(reqs)} requests equal alone and in the mix, and the oracle on sampled rows")
+    srv.close()
+    g.detach_memo()

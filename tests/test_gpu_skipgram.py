@@ -1,0 +1,137 @@
+"""Skip-gram step on the GPU (bf16 MFMA, fp32 accumulation) against the oracle's
+fp64 step on the same inputs, within a bound derived from the arithmetic.
+
+Bound (per element, from the rounding the kernel performs): the table values are
+rounded to bf16 (unit roundoff u = 2^-9), so each logit z = sum_d v_d t_d carries
+at most (2u + u^2 + 128 * 2^-24) * sum_d |v_d t_d| of error; a coefficient
+(sigmoid, derivative at most 1/4, times neg_weight for negatives) at most a
+quarter of that, plus 2^-20 |g| for the fp32 exponential; the coefficient is
+rounded to bf16 again (u); each gradient element sum_t g_t x_t then errs by at
+most sum_t (dg_t + u |g_t|) |x_t| (1 + u) + (u + K 2^-24) sum_t |g_t x_t|, and
+the fp32 atomic sums over a row's contributions by 2^-20 of their absolute sum.
+The update w - lr g adds 2^-23 (|w| + lr |g|).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import skipgram as SG
+import paper_1805_00280_amd as P
+from gpuhelp import oracle_rmat, oracle_walk, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -9
+
+
+def noise_table(og):
+    w = np.floor(np.power(og.degree().astype(np.float64), 0.75) * 1024.0).astype(np.uint64)
+    return np.concatenate([[0], np.cumsum(w)]).astype(np.uint64)
+
+
+def bounds(win, wout, walks, negs, window, lam):
+    win, wout = win.astype(np.float64), wout.astype(np.float64)
+    bin_, bout = np.zeros_like(win), np.zeros_like(wout)
+    sin, sout = np.zeros_like(win), np.zeros_like(wout)
+    lb = 0.0
+    for w, row in enumerate(walks):
+        n = SG.walk_length(row)
+        if n == 0:
+            continue
+        ids = row[:n].astype(np.int64)
+        tids = np.concatenate([ids, negs[w].astype(np.int64)])
+        V, T = win[ids], wout[tids]
+        Z = V @ T.T
+        A = np.abs(V) @ np.abs(T).T
+        dz = (2 * U + U * U + 128 * 2.0 ** -24) * A
+        dist = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :])
+        mult = np.zeros_like(Z)
+        mult[:, :n] = ((dist >= 1) & (dist <= window)).astype(np.float64)
+        mult[:, n:] = lam
+        G = np.zeros_like(Z)
+        G[:, :n] = np.where(mult[:, :n] > 0, SG.sigmoid(Z[:, :n]) - 1.0, 0.0)
+        G[:, n:] = lam * SG.sigmoid(Z[:, n:])
+        dg = 0.25 * dz * mult + 2.0 ** -20 * np.abs(G)
+        gb = dg + U * np.abs(G)
+        aG = np.abs(G)
+        dV = gb @ np.abs(T) * (1 + U) + (aG @ np.abs(T)) * (U + 160 * 2.0 ** -24)
+        dT = gb.T @ np.abs(V) * (1 + U) + (aG.T @ np.abs(V)) * (U + 96 * 2.0 ** -24)
+        np.add.at(bin_, ids, dV)
+        np.add.at(bout, tids, dT)
+        np.add.at(sin, ids, aG @ np.abs(T))
+        np.add.at(sout, tids, aG.T @ np.abs(V))
+        lb += float((dz * mult).sum())
+    return bin_ + 2.0 ** -20 * sin, bout + 2.0 ** -20 * sout, lb
+
+
+def run_case(og, walks, window, nneg, lr, seed, step, rng):
+    torch = torch_cuda()
+    n, D = og.n, 128
+    win = (rng.standard_normal((n, D)) * 0.12).astype(np.float32)
+    wout = (rng.standard_normal((n, D)) * 0.12).astype(np.float32)
+    cum = noise_table(og)
+    sg = P.SkipGram(n, torch.from_numpy(win.copy()).cuda(), torch.from_numpy(wout.copy()).cuda(),
+                    torch.from_numpy(cum.view(np.int64)).cuda(), window=window, negatives=nneg, lr=lr, seed=seed,
+                    max_walks=len(walks))
+    lam = sg.prm.neg_weight
+    negs_gpu = sg.negatives(len(walks), walk_base=0, step=step).cpu().numpy().view(np.uint32)
+    negs = SG.negatives(cum, seed, 0, len(walks), nneg, step)
+    assert np.array_equal(negs_gpu, negs), "negatives differ from the oracle's"
+    wt = torch.from_numpy(np.ascontiguousarray(walks).view(np.int32)).cuda()
+    sg.step(wt, walk_base=0, step=step)
+    torch.cuda.synchronize()
+    gwin, gwout = sg.win.cpu().numpy(), sg.wout.cpu().numpy()
+    gloss = float(sg.loss.cpu().numpy()[0])
+    owin, owout, oloss, ogin, ogout = SG.step(win, wout, walks, negs, window, lam, lr)
+    bi, bo, bl = bounds(win, wout, walks, negs, window, lam)
+    for got, want, b, g, w0, name in ((gwin, owin, bi, ogin, win, "win"), (gwout, owout, bo, ogout, wout, "wout")):
+        tol = lr * b + 2.0 ** -23 * (np.abs(w0) + lr * np.abs(g)) + 1e-12
+        err = np.abs(got.astype(np.float64) - want)
+        worst = float((err / tol).max())
+        touched = np.abs(g) > 0
+        rel = np.median((b[touched]) / (np.abs(g[touched]) + 1e-30))
+        say(f"[sgns] {name}: max error / bound {worst:.3f}, median bound / |gradient| {rel:.4f}, "
+            f"max error {err.max():.3g}")
+        assert worst <= 1.0, f"{name} outside the derived bound"
+        assert rel < 0.25, "the bound is too loose to pin anything"
+    say(f"[sgns] loss gpu {gloss:.6f} oracle {oloss:.6f} bound {bl:.3g}")
+    assert abs(gloss - oloss) <= bl + 1e-6 * abs(oloss)
+    return sg
+
+
+def test_skipgram_step_on_walks_of_the_walk_engine_shape():
+    # 80-move walks of a scale-10 R-MAT graph (r = 2), window 10, 64 shared negatives
+    og = oracle_rmat(10, 16, 0.57, 0.19, 0.19, 10, False)
+    starts = np.tile(np.arange(og.n, dtype=np.uint32), 2)
+    walks = oracle_walk(og, starts, 80, 0.5, 2.0, 3)
+    run_case(og, walks, 10, 64, 0.025, 77, 5, np.random.default_rng(1))
+
+
+def test_skipgram_step_with_short_rows_and_partial_negatives():
+    # rows of 20 entries with sentinel tails and isolated starts, window 5, 17 negatives
+    og = oracle_rmat(11, 8, 0.65, 0.15, 0.15, 11, False)
+    starts = np.arange(0, og.n, 2, dtype=np.uint32)
+    walks = oracle_walk(og, starts, 19, 2.0, 0.5, 4)
+    assert (walks == O.SENT).any()
+    run_case(og, walks, 5, 17, 0.05, 5, 0, np.random.default_rng(2))
+
+
+def test_skipgram_two_steps_keep_the_workspace_clean():
+    # a second step with the same workspace starts from zero gradients: equal to the oracle
+    # applied twice
+    torch = torch_cuda()
+    og = oracle_rmat(9, 16, 0.57, 0.19, 0.19, 9, False)
+    walks = oracle_walk(og, np.arange(og.n, dtype=np.uint32), 30, 1.0, 1.0, 5)
+    rng = np.random.default_rng(3)
+    sg = run_case(og, walks, 4, 32, 0.05, 9, 0, rng)
+    win1, wout1 = sg.win.cpu().numpy().copy(), sg.wout.cpu().numpy().copy()
+    sg.loss.zero_()
+    wt = torch.from_numpy(np.ascontiguousarray(walks).view(np.int32)).cuda()
+    sg.step(wt, walk_base=0, step=1)
+    torch.cuda.synchronize()
+    negs = SG.negatives(noise_table(og), 9, 0, len(walks), 32, 1)
+    owin, owout, _, ogin, ogout = SG.step(win1, wout1, walks, negs, 4, sg.prm.neg_weight, 0.05)
+    bi, bo, _ = bounds(win1, wout1, walks, negs, 4, sg.prm.neg_weight)
+    for got, want, b, g, w0 in ((sg.win.cpu().numpy(), owin, bi, ogin, win1), (sg.wout.cpu().numpy(), owout, bo, ogout, wout1)):
+        tol = 0.05 * b + 2.0 ** -23 * (np.abs(w0) + 0.05 * np.abs(g)) + 1e-12
+        assert (np.abs(got - want) <= tol).all()

@@ -1,6 +1,7 @@
 """Planted mistakes in copies of the oracle are caught by the pins (CPU only).
 
-Each case edits one line of a private copy of oracle.c, builds it under /tmp,
+Each case edits one line of a private copy of the oracle (oracle.c unless
+another file is named), builds it under /tmp,
 and runs a subset of the pin tests against it in a subprocess; the subset
 must fail.  The committed oracle is never modified.
 """
@@ -80,22 +81,39 @@ MUTATIONS = [
      "while ((16ull << k) < d) ++k;", "while ((16ull << k) <= d) ++k;"),
     ("memo: summary read even when dearer",
      "            if (warm < cold) {", "            if (warm < cold + 1000000) {"),
+    # the Skip-gram step that consumes the walks
+    ("sgns: negatives drawn with another counter tag",
+     "ph(seed, (uint32_t)(walk_base + i), k, step, 6, r);", "ph(seed, (uint32_t)(walk_base + i), k, step, 5, r);"),
+    ("sgns: a center is its own context",
+     "pos = (dist >= 1) & (dist <= window)", "pos = dist <= window", "skipgram.py"),
+    ("sgns: context window one short",
+     "pos = (dist >= 1) & (dist <= window)", "pos = (dist >= 1) & (dist < window)", "skipgram.py"),
+    ("sgns: negative weight missing from the gradient",
+     "G[:, n:] = neg_weight * sigmoid(Z[:, n:])", "G[:, n:] = sigmoid(Z[:, n:])", "skipgram.py"),
+    ("sgns: context gradient with the wrong sign",
+     "np.where(pos, sigmoid(Z[:, :n]) - 1.0, 0.0)", "np.where(pos, 1.0 - sigmoid(Z[:, :n]), 0.0)", "skipgram.py"),
+    ("sgns: target gradient from the wrong vectors",
+     "np.add.at(gout, tids, G.T @ V)", "np.add.at(gout, tids, G.T @ (0.5 * V))", "skipgram.py"),
 ]
 
 TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_rmat.py", "tests/test_oracle_law.py",
-         "tests/test_oracle_invariants.py", "tests/test_oracle_approx.py", "tests/test_oracle_cost.py"]
+         "tests/test_oracle_invariants.py", "tests/test_oracle_approx.py", "tests/test_oracle_cost.py",
+         "tests/test_oracle_skipgram.py"]
 
 
-@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_planted_mistake_is_caught(name, old, new):
-    src = open(SRC).read()
+@pytest.mark.parametrize("mutation", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(mutation):
+    name, old, new = mutation[:3]
+    fname = mutation[3] if len(mutation) > 3 else "oracle.c"
+    path = os.path.join(ROOT, "oracle", fname)
+    src = open(path).read()
     assert src.count(old) == 1, name
     tmp = tempfile.mkdtemp(prefix="n2v_mut_")
     try:
         pkg = os.path.join(tmp, "oracle")
         shutil.copytree(os.path.join(ROOT, "oracle"), pkg,
                         ignore=shutil.ignore_patterns("*.so", "__pycache__"))
-        with open(os.path.join(pkg, "oracle.c"), "w") as f:
+        with open(os.path.join(pkg, fname), "w") as f:
             f.write(src.replace(old, new))
         subprocess.check_call([sys.executable, os.path.join(pkg, "build.py")],
                               stdout=subprocess.DEVNULL)

@@ -46,3 +46,35 @@ def test_wec20_matches_table1():
     assert abs(og.m - m_paper) / m_paper < 0.005
     assert dmax_paper / 2 <= int(deg.max()) <= 2 * dmax_paper
     assert abs(deg.mean() - 100.0) < 0.1
+
+
+def test_request_stream_philox_matches_the_reference_copy():
+    # the input generator's vectorised Philox against the pure-Python copy
+    from oracle.philox_ref import philox4x32
+    rng = np.random.default_rng(2)
+    c = rng.integers(0, 2**32, size=(4, 500), dtype=np.uint64)
+    k0, k1 = 0x1234567, 0x89ABCDEF
+    got = WL.philox_np(k0, k1, *c)
+    for i in range(500):
+        want = philox4x32((k0, k1), [int(x) for x in c[:, i]])
+        assert [int(g[i]) for g in got] == want
+
+
+def test_request_stream_shape():
+    # sizes floor(2^(20U)) in [1, 2^20] (mean about (2^20 - 1) / (20 ln 2) = 75.6K), L in
+    # {20, 40, 80}, p and q over five values, starts below n; the stream is reproducible
+    n = 1 << 22
+    reqs = [WL.serving_request(j, n) for j in range(200)]
+    sizes = np.array([len(r["starts"]) for r in reqs])
+    assert sizes.min() >= 1 and sizes.max() <= 1 << 20
+    logs = np.log2(sizes + 1)
+    assert 8.0 < logs.mean() < 12.0
+    assert {r["L"] for r in reqs} == {20, 40, 80}
+    assert {r["p"] for r in reqs} == {0.25, 0.5, 1.0, 2.0, 4.0} == {r["q"] for r in reqs}
+    assert all(int(r["starts"].max()) < n for r in reqs)
+    again = WL.serving_request(17, n)
+    assert np.array_equal(again["starts"], reqs[17]["starts"]) and again["seed"] == reqs[17]["seed"]
+    big = WL.serving_request(3, n, size=1 << 20)
+    assert len(big["starts"]) == 1 << 20 and abs(big["starts"].mean() / n - 0.5) < 0.01
+    t = WL.arrival_times(reqs, rate=100.0)
+    assert np.all(np.diff(t) > 0) and 1.2 < t[-1] < 2.8
