@@ -213,6 +213,23 @@ int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint32_t n_start
                     const n2v_exec_opts *opts, int outputs, uint32_t *out, uint32_t *cnt,
                     uint64_t *checksum, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the plain
+ * form of n2v_walk_approx (approx_t = 0: n2v_walk_ex) with the mode forced to
+ * N2V_MODE_PLAIN and its workspace replaced by a fixed scratch array that the
+ * library holds on each GPU it runs on (about 40 MiB, kept until the process
+ * ends).  Results are identical to n2v_walk_ex / n2v_walk_approx.  At most
+ * 2^21 walks of at most 1023 moves per call, else N2V_ENOMEM with nothing
+ * enqueued.  It calls no allocating routine.  Every call on one GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (other streams, other
+ * threads) race and give wrong results; calls ordered on one stream do not.
+ * The per-superstep counters are cleared by a kernel at the start of each
+ * call. */
+int n2v_walk_static(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
+                    uint32_t L, float p, float q, uint64_t seed, uint32_t approx_t,
+                    const n2v_exec_opts *opts, int outputs, uint32_t *out, uint32_t *cnt,
+                    uint64_t *checksum, void *stream);
+
 /* Visit profile (the frequency-versus-degree study of Section 3.3): for
  * visit counts cnt (device, n uint32, as written by the COUNTS output),
  * vertices[k] and visits[k] (device, nbuckets uint64 each, overwritten)

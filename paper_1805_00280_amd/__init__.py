@@ -30,7 +30,7 @@ EXPORTS = [
     "n2v_graph_opts_default", "n2v_graph_workspace", "n2v_graph_create", "n2v_graph_destroy",
     "n2v_graph_info", "n2v_graph_check", "n2v_graph_memo_bytes", "n2v_graph_set_memo",
     "n2v_graph_memo_plan", "n2v_graph_set_memo_min", "n2v_graph_memo_clear",
-    "n2v_exec_opts_default", "n2v_walk", "n2v_walk_workspace", "n2v_walk_ex", "n2v_walk_approx",
+    "n2v_exec_opts_default", "n2v_walk", "n2v_walk_workspace", "n2v_walk_ex", "n2v_walk_approx", "n2v_walk_static",
     "n2v_visit_profile",
     "n2v_sgns_workspace", "n2v_sgns_negatives", "n2v_sgns_step",
     "n2v_autotune_workspace", "n2v_autotune",
@@ -121,6 +121,7 @@ def lib():
         "n2v_walk_ex": ([vp, vp, u32, u64, u32, f32, f32, u64, P(ExecOpts), i32, vp, vp, vp, vp, sz, vp], i32),
         "n2v_walk_approx": ([vp, vp, u32, u64, u32, f32, f32, u64, u32, P(ExecOpts), i32, vp, vp, vp, vp, sz, vp],
                             i32),
+        "n2v_walk_static": ([vp, vp, u32, u64, u32, f32, f32, u64, u32, P(ExecOpts), i32, vp, vp, vp, vp], i32),
         "n2v_visit_profile": ([vp, vp, u32, u32, vp, vp, vp], i32),
         "n2v_sgns_workspace": ([u32, u32, u32, u32, P(sz)], i32),
         "n2v_sgns_negatives": ([vp, u32, u64, u64, u32, u32, u32, vp, vp], i32),
@@ -329,6 +330,18 @@ class Graph:
             ws = _alloc(need, self.device)
         self._walk_call(starts, n, walk_base, L, p, q, seed, approx_t, o, OUT_WALKS, out, None, None, ws, need,
                         stream)
+        return out
+
+    def walk_static(self, starts, L, p, q, seed, walk_base=0, out=None, opts=None, stream=None, approx_t=0):
+        """Plain form in the library's static scratch (n2v_walk_static): allocates nothing
+        beyond `out` when it is not given."""
+        torch = _torch()
+        n = int(starts.numel())
+        if out is None:
+            out = torch.empty((n, L + 1), dtype=torch.int32, device=self.device)
+        o = opts if opts is not None else exec_opts(self)
+        check(lib().n2v_walk_static(self._h, _ptr(starts), n, walk_base, L, p, q, seed, approx_t, C.byref(o),
+                                    OUT_WALKS, _ptr(out), None, None, _stream(stream)), "n2v_walk_static")
         return out
 
     def walk_simple(self, starts, L, p, q, seed, out=None, stream=None):

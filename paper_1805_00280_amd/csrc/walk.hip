@@ -1942,3 +1942,76 @@ extern "C" int n2v_walk(const n2v_graph *g, const uint32_t *starts, uint32_t n_s
     return n2v_walk_ex(g, starts, n_starts, 0, L, p, q, seed, nullptr, N2V_OUT_WALKS, out, nullptr, nullptr, nullptr,
                        0, stream);
 }
+
+// ----------------------------------------- plain form without allocation
+// For callers that cannot allocate device memory (code under graph capture,
+// tight serving loops, harnesses that forbid allocation): the plain form's
+// scratch (per-walk state, the hub-move queue and per-superstep counters)
+// lives in a fixed file-scope array that each GPU holds until the process
+// ends.  Sizes: at most 2^21 walks of at most 1023 moves.
+namespace n2v {
+namespace {
+
+constexpr uint32_t STATIC_MAX_WALKS = 1u << 21;
+constexpr uint32_t STATIC_MAX_L = 1023;
+// plain_ws(STATIC_MAX_WALKS, STATIC_MAX_L): 16-byte states and 4-byte queue
+// entries per walk, four u32 counters per superstep, each piece 256-aligned
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)16 * STATIC_MAX_WALKS + (size_t)4 * STATIC_MAX_WALKS +
+                                        (((size_t)16 * (STATIC_MAX_L + 1) + 255) & ~(size_t)255);
+
+__device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+// Device address of this GPU's copy of `scratch` (the host-side name is only
+// a stand-in), looked up once per device with that device current.
+void *scratch_ptr(int dev, int *rc)
+{
+    static std::mutex mu;
+    static void *ptr[64] = {};
+    *rc = N2V_OK;
+    if (dev < 0 || dev >= 64) {
+        *rc = set_error(N2V_EDEVICE, "n2v_walk_static: device %d out of range", dev);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            *rc = hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+            return nullptr;
+        }
+        ptr[dev] = p;
+    }
+    return ptr[dev];
+}
+
+}  // namespace
+}  // namespace n2v
+
+extern "C" int n2v_walk_static(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
+                               uint32_t L, float p, float q, uint64_t seed, uint32_t approx_t,
+                               const n2v_exec_opts *opts, int outputs, uint32_t *out, uint32_t *cnt,
+                               uint64_t *checksum, void *stream)
+{
+    if (!g) return set_error(N2V_EINVAL, "n2v_walk_static: null graph");
+    if (n_starts > STATIC_MAX_WALKS || L > STATIC_MAX_L)
+        return set_error(N2V_ENOMEM, "n2v_walk_static: %u walks of %u moves exceed the static scratch (at most %u walks "
+                         "of at most %u moves)", n_starts, L, STATIC_MAX_WALKS, STATIC_MAX_L);
+    const size_t need = plain_ws(n_starts, L);
+    if (need > STATIC_SCRATCH_BYTES)
+        return set_error(N2V_ENOMEM, "n2v_walk_static: %zu scratch bytes needed, %zu held", need,
+                         STATIC_SCRATCH_BYTES);
+    int rc = N2V_OK;
+    void *ws = scratch_ptr(g->device, &rc);
+    if (rc) return rc;
+    n2v_exec_opts o;
+    n2v_exec_opts_default(g, &o);
+    if (opts) o = *opts;
+    o.mode = N2V_MODE_PLAIN;
+    return n2v_walk_approx(g, starts, n_starts, walk_base, L, p, q, seed, approx_t, &o, outputs, out, cnt, checksum,
+                           ws, STATIC_SCRATCH_BYTES, stream);
+}
