@@ -240,16 +240,18 @@ int n2v_walk_static(const n2v_graph *g, const uint32_t *starts, uint32_t n_start
 int n2v_visit_profile(const n2v_graph *g, const uint32_t *cnt, uint32_t width, uint32_t nbuckets,
                       uint64_t *vertices, uint64_t *visits, void *stream);
 
-/* Pair sketches (unweighted graphs; the FN-Cache paragraph of Section 3.4
- * keeps work done for popular vertices for reuse): memory in which walk calls
- * memoise, for every traversed move (t -> v) at a vertex v of degree >
- * d_rule, the exact number of members of N(t) in each of 64 equal segments
- * of N(v) and in each segment's first half (as count + 1; 0 = unknown), and
- * for each segment a hint where its merge may start in N(t).  A later move
+/* Pair sketches (the FN-Cache paragraph of Section 3.4 keeps work done for
+ * popular vertices for reuse): memory in which walk calls memoise, for every
+ * traversed move (t -> v) at a vertex v of degree > d_rule, the exact number
+ * of members of N(t) in each of 64 equal segments of N(v) and in each
+ * segment's first half (as count + 1; 0 = unknown), and for each segment a
+ * hint where its merge may start in N(t); on weighted graphs also, per
+ * segment and per first half, the weight sum of those members (+ 1) and of
+ * all entries (u32 words after the u16 ones).  A later move
  * along the same pair then recomputes half a segment instead of the whole
  * intersection.  Rows of degree above 4,161,536 (127 x 512 x 64) keep no
- * sketches.  A merge for (t -> v) also fills the sketch of (v -> t) when t
- * has degree > d_rule.  Results never depend on the sketches: unknown
+ * sketches.  On unweighted graphs a merge for (t -> v) also fills the sketch
+ * of (v -> t) when t has degree > d_rule.  Results never depend on the sketches: unknown
  * entries are recomputed, and every known entry is exact (hints never point
  * past the segment's first candidate).
  * Sketches describe the graph only (not p, q, seed or the walks), so they
@@ -257,9 +259,9 @@ int n2v_visit_profile(const n2v_graph *g, const uint32_t *cnt, uint32_t width, u
  * and fills the same memory, and overlapping calls only ever write equal
  * values into an entry.  Attaching clears the memory; n2v_graph_memo_clear
  * makes later calls start from unknown entries again (a cold pass).
- * n2v_graph_memo_bytes returns the size (hub entries x 384 bytes; 0 for
- * weighted graphs); n2v_graph_set_memo attaches caller device memory (NULL
- * detaches).  Attaching synchronises the device, and returns N2V_EINVAL,
+ * n2v_graph_memo_bytes returns the size (hub entries x 384 bytes, or x 1408
+ * for weighted graphs); n2v_graph_set_memo attaches caller device memory
+ * (NULL detaches).  Attaching synchronises the device, and returns N2V_EINVAL,
  * changing nothing, while a server created on the graph is alive. */
 int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes);
 int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes);
@@ -273,8 +275,8 @@ int n2v_graph_memo_clear(n2v_graph *g, void *stream);
  * at vertices of degree >= min_degree (> d_rule) keep sketches; the other hub
  * moves take the full pass every time.  n2v_graph_memo_plan returns the
  * smallest such threshold whose rows fit in `budget` bytes, and those rows'
- * bytes (*min_degree = 0xFFFFFFFF and *bytes = 0 when none fit; weighted
- * graphs: N2V_EINVAL).  It allocates nothing (its degree statistics use the
+ * bytes (*min_degree = 0xFFFFFFFF and *bytes = 0 when none fit).  It
+ * allocates nothing (its degree statistics use the
  * graph's workspace) and synchronises the device, so plans on one graph must
  * not run concurrently.
  * n2v_graph_set_memo_min attaches `bytes` of device memory (256-byte aligned)

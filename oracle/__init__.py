@@ -67,7 +67,7 @@ def _load():
     lib.or_memo_pair_lines.restype = u64
     lib.or_memo_cold_lines.argtypes = [vp, i32, u32, u32]
     lib.or_memo_cold_lines.restype = u64
-    lib.or_memo_warm_lines.argtypes = [vp, u32, u32]
+    lib.or_memo_warm_lines.argtypes = [vp, i32, u32, u32]
     lib.or_memo_warm_lines.restype = u64
     lib.or_memo_pass_bytes.argtypes = [vp, i32, vp, u64, u32, u32, u32, i32, vp]
     lib.or_memo_pass_bytes.restype = i32
@@ -305,9 +305,9 @@ def memo_cold_lines(off, t, v, weighted=False):
     return int(_load().or_memo_cold_lines(_ptr(off), int(weighted), t, v))
 
 
-def memo_warm_lines(off, t, v):
+def memo_warm_lines(off, t, v, weighted=False):
     off = np.ascontiguousarray(off, dtype=np.uint64)
-    return int(_load().or_memo_warm_lines(_ptr(off), t, v))
+    return int(_load().or_memo_warm_lines(_ptr(off), int(weighted), t, v))
 
 
 def memo_pass_bytes(off, out, L, d_rule=D_RULE, memo_min=None, memo=True, weighted=False):

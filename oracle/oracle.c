@@ -965,14 +965,17 @@ uint64_t or_memo_cold_lines(const uint64_t *off, int weighted, uint32_t t, uint3
     return search < dense ? search : dense;
 }
 
-/* Lines of one move at v after t that reads a summary. */
-uint64_t or_memo_warm_lines(const uint64_t *off, uint32_t t, uint32_t v)
+/* Lines of one move at v after t that reads a summary.  A weighted graph's */
+/* summary row also holds four 32-bit weight sums per segment (22 lines),   */
+/* and the half segment's weights are read with its entries.               */
+uint64_t or_memo_warm_lines(const uint64_t *off, int weighted, uint32_t t, uint32_t v)
 {
     uint64_t dv = off[v + 1] - off[v], dt = off[t + 1] - off[t];
     uint64_t tiles = (dv + 511) / 512;
     uint64_t seglen = ((tiles + 63) / 64) * 512;
     uint64_t h = seglen / 2 < dv ? seglen / 2 : dv;
     uint64_t ht = (dt * h + dv - 1) / dv;
+    if (weighted) return 22 + (4 * h + 63) / 64 + (2 * h + 63) / 64 + (4 * ht + 63) / 64;
     return 6 + (4 * h + 63) / 64 + (4 * ht + 63) / 64;
 }
 
@@ -985,8 +988,10 @@ static int or_memo_keeps(uint64_t d, uint32_t memo_min)
 /* above d_rule (cold and warm, intersections included), res[1] = those     */
 /* moves, res[2] = all other moves (first moves and moves at vertices of    */
 /* degree <= d_rule), res[3] = intersections charged, res[4] = warm moves.  */
-/* memo = 0 or a weighted graph: no summaries.  Returns -1 on allocation    */
-/* failure.                                                                 */
+/* memo = 0: no summaries.  A weighted graph's summary of (t -> v) also     */
+/* holds weight sums of N(v), so it serves that direction only and costs   */
+/* the directed cold evaluation (weights of N(v) included) to build.       */
+/* Returns -1 on allocation failure.                                        */
 int or_memo_pass_bytes(const uint64_t *off, int weighted, const uint32_t *out, uint64_t count, uint32_t L,
                        uint32_t d_rule, uint32_t memo_min, int memo, uint64_t res[5])
 {
@@ -994,7 +999,7 @@ int or_memo_pass_bytes(const uint64_t *off, int weighted, const uint32_t *out, u
     uint64_t *keys = (uint64_t *)malloc(cap * sizeof(uint64_t));
     if (!keys) return -1;
     memset(res, 0, 5 * sizeof(uint64_t));
-    int summaries = memo && !weighted;
+    int summaries = memo;
     for (uint64_t i = 0; i < count; ++i) {
         const uint32_t *row = out + i * (uint64_t)(L + 1);
         for (uint32_t s = 0; s < L; ++s) {
@@ -1006,13 +1011,13 @@ int or_memo_pass_bytes(const uint64_t *off, int weighted, const uint32_t *out, u
             res[1] += 1;
             uint64_t lines = or_memo_off_lines(v);
             uint64_t cold = or_memo_cold_lines(off, weighted, t, v);
-            uint64_t warm = summaries && or_memo_keeps(dv, memo_min) ? or_memo_warm_lines(off, t, v) : cold;
+            uint64_t warm = summaries && or_memo_keeps(dv, memo_min) ? or_memo_warm_lines(off, weighted, t, v) : cold;
             if (warm < cold) {
                 lines += warm;
                 res[4] += 1;
                 uint64_t dt = off[t + 1] - off[t];
                 uint64_t key;
-                if (or_memo_keeps(dt, memo_min))
+                if (!weighted && or_memo_keeps(dt, memo_min))
                     key = t < v ? ((uint64_t)t << 32) | v : ((uint64_t)v << 32) | t;
                 else
                     key = ((uint64_t)v << 32) | t;
@@ -1034,7 +1039,8 @@ int or_memo_pass_bytes(const uint64_t *off, int weighted, const uint32_t *out, u
         for (uint64_t k = 0; k < nk; ++k) {
             if (k > 0 && keys[k] == keys[k - 1]) continue;
             uint32_t a = (uint32_t)(keys[k] >> 32), b = (uint32_t)keys[k];
-            res[0] += or_memo_pair_lines(off, a, b) * 64;
+            /* weighted keys are (v, t) */
+            res[0] += (weighted ? or_memo_cold_lines(off, 1, b, a) : or_memo_pair_lines(off, a, b)) * 64;
             res[3] += 1;
         }
     }

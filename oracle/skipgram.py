@@ -14,7 +14,9 @@ negatives shared by all of its centers):
   - the gradient of that loss: d/dz = sigmoid(z) - 1 for a context and
     neg_weight * sigmoid(z) for a negative, times u for the center's vector
     and times v for the target's, summed over the whole batch;
-  - win -= lr * dL/dwin, wout -= lr * dL/dwout, after the whole batch.
+  - after the whole batch, each row moves by lr times its mean gradient per
+    occurrence in the batch: w[x] -= lr * dL/dw[x] / (occurrences of x as a
+    center, resp. as a target, at least 1).
 Negatives come from the oracle's C draw (or_sgns_negatives: Philox and the
 cumulative noise table).  Shares nothing with the GPU library.
 """
@@ -55,11 +57,14 @@ def sigmoid(x):
 
 
 def step(win, wout, walks, negs, window, neg_weight, lr):
-    """One step; returns (new win, new wout, loss, gradient of win, gradient of wout), fp64."""
+    """One step; returns (new win, new wout, loss, gradient of win, gradient of wout,
+    occurrences as centers, occurrences as targets), fp64."""
     win = np.asarray(win, dtype=np.float64)
     wout = np.asarray(wout, dtype=np.float64)
     gin = np.zeros_like(win)
     gout = np.zeros_like(wout)
+    cin = np.zeros(len(win))
+    cout = np.zeros(len(wout))
     loss = 0.0
     for w, row in enumerate(np.asarray(walks, dtype=np.uint32)):
         n = walk_length(row)
@@ -81,4 +86,8 @@ def step(win, wout, walks, negs, window, neg_weight, lr):
         loss += float(softplus(-Z[:, :n])[pos].sum() + neg_weight * softplus(Z[:, n:]).sum())
         np.add.at(gin, ids, G @ T)
         np.add.at(gout, tids, G.T @ V)
-    return win - lr * gin, wout - lr * gout, loss, gin, gout
+        np.add.at(cin, ids, 1.0)
+        np.add.at(cout, tids, 1.0)
+    sin = lr / np.maximum(cin, 1.0)
+    sout = lr / np.maximum(cout, 1.0)
+    return win - sin[:, None] * gin, wout - sout[:, None] * gout, loss, gin, gout, cin, cout

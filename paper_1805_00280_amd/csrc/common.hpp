@@ -21,8 +21,14 @@ constexpr int WAVE = 64;
 // (MEMO_ROW u16 per sketch).
 constexpr int MEMO_SEGS = 64;
 constexpr int MEMO_ROW = 3 * MEMO_SEGS;
+// Rows of weighted graphs append, as u32 after the 3 x MEMO_SEGS u16 words,
+// per segment the weight sum of its members of N(t), the same over its first
+// half, the weight sum of all its entries and the same over its first half.
+constexpr int MEMO_ROW_W = 3 * MEMO_SEGS + 8 * MEMO_SEGS;
+__host__ __device__ constexpr int memo_row_words(bool weighted) { return weighted ? MEMO_ROW_W : MEMO_ROW; }
 // Sketches serve rows of at most this degree: 127 tiles of 512 entries per
-// segment, so count + 1 always fits the u16 entries.
+// segment, so count + 1 always fits the u16 entries (and a segment's weight
+// sum, at most 65024 x 65535, a u32).
 constexpr uint32_t MEMO_MAX_DEG = 127u * 512u * MEMO_SEGS;
 // Walk counters a graph hands out round-robin to persistent launches: up to
 // this many launches on one graph may overlap.

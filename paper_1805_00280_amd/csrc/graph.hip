@@ -322,7 +322,7 @@ extern "C" int n2v_graph_info(const n2v_graph *g, uint32_t *n, uint64_t *m, uint
 extern "C" int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes)
 {
     if (!g || !bytes) return set_error(N2V_EINVAL, "n2v_graph_memo_bytes: null argument");
-    *bytes = g->weighted ? 0 : (size_t)g->hub_entries * MEMO_ROW * sizeof(uint16_t);
+    *bytes = (size_t)g->hub_entries * memo_row_words(g->weighted) * sizeof(uint16_t);
     return N2V_OK;
 }
 
@@ -352,8 +352,7 @@ unsigned long long deg_sum_ge(const n2v_graph *g, uint64_t dmin, int *rc)
 extern "C" int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *min_degree, size_t *bytes)
 {
     if (!g || !min_degree || !bytes) return set_error(N2V_EINVAL, "n2v_graph_memo_plan: null argument");
-    if (g->weighted) return set_error(N2V_EINVAL, "n2v_graph_memo_plan: weighted graphs keep no pair sketches");
-    const size_t row = MEMO_ROW * sizeof(uint16_t);
+    const size_t row = memo_row_words(g->weighted) * sizeof(uint16_t);
     const uint64_t dmin = (uint64_t)g->dg.d_rule + 1;
     if (g->hub_entries * row <= budget) {
         *min_degree = (uint32_t)std::min<uint64_t>(dmin, 0xFFFFFFFFull);
@@ -436,7 +435,6 @@ extern "C" int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uin
         g->memo_bytes = 0;
         return N2V_OK;
     }
-    if (g->weighted) return set_error(N2V_EINVAL, "n2v_graph_set_memo: weighted graphs keep no pair sketches");
     if (((uintptr_t)mem & 255) != 0) return set_error(N2V_EINVAL, "n2v_graph_set_memo: memory not 256-byte aligned");
     const uint64_t dmin = std::max<uint64_t>(min_degree, (uint64_t)g->dg.d_rule + 1);
     // the rows the threshold keeps are counted before anything changes, so a
@@ -447,7 +445,7 @@ extern "C" int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uin
         rows = deg_sum_ge(g, dmin, &rc);
         if (rc) return rc;
     }
-    const size_t need = (size_t)rows * MEMO_ROW * sizeof(uint16_t);
+    const size_t need = (size_t)rows * memo_row_words(g->weighted) * sizeof(uint16_t);
     if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
     // detached while the rows are re-indexed: a failure below leaves no
     // memory attached rather than memory indexed for another threshold
@@ -485,7 +483,7 @@ extern "C" int n2v_graph_set_memo(n2v_graph *g, void *mem, size_t bytes)
     size_t need = 0;
     n2v_graph_memo_bytes(g, &need);
     if (need == 0)
-        return set_error(N2V_EINVAL, "n2v_graph_set_memo: no pair sketches (weighted graph, or no row above d_rule)");
+        return set_error(N2V_EINVAL, "n2v_graph_set_memo: no pair sketches (no row above d_rule)");
     if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
     return n2v_graph_set_memo_min(g, mem, bytes, g->dg.d_rule + 1 > g->dg.d_rule ? g->dg.d_rule + 1 : g->dg.d_rule);
 }

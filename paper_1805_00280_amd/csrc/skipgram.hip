@@ -14,7 +14,8 @@
 //   - gradient coefficients g = sigmoid(z) - 1 (context) and
 //     neg_weight * sigmoid(z) (negative); dv = sum g u, du = sum g v;
 //   - after every walk of the batch is evaluated against the same tables, both
-//     tables take one SGD step: w -= lr * gradient.
+//     tables take one SGD step in which each row moves by its mean gradient
+//     per occurrence in the batch: w -= lr * gradient / occurrences.
 // Per walk the three contractions (logits, center gradients, target
 // gradients) are dense products of at most 96 centers by 160 targets by 128
 // dimensions; one workgroup evaluates them with bf16 MFMA (fp32 accumulate)
@@ -47,6 +48,7 @@ struct SgArgs {
     const uint32_t *negs;    // n_walks x nneg
     const float *win, *wout; // n x SG_DIM
     float *gin, *gout;       // n x SG_DIM gradient accumulators
+    float *cin, *cout;       // n occurrence counts of each row in the batch
     double *loss;
     uint32_t n_walks, row_len, nneg, window;
     float neg_weight;
@@ -111,27 +113,51 @@ __global__ __launch_bounds__(SG_BLOCK, 1) void k_sg_walks(SgArgs A)
     __syncthreads();
     uint32_t len = 0;
     while (len < A.row_len && S.ids[len] != SENT) ++len;
-    // rows to bf16 tiles, row-major and transposed: 32 lanes per row, 4 floats each
-    for (int r = tid / 32; r < SG_MAXC + SG_T; r += SG_BLOCK / 32) {
-        const int q = tid & 31;
-        const bool center = r < SG_MAXC;
-        const int t = center ? r : r - SG_MAXC;
-        const uint32_t id = S.ids[t];
-        const bool valid = center ? (uint32_t)r < len : (t < SG_MAXC ? (uint32_t)t < len : (uint32_t)(t - SG_MAXC) < A.nneg);
-        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (valid) x = *(const float4 *)((center ? A.win : A.wout) + (uint64_t)id * SG_DIM + 4 * q);
-        const __bf16 b0 = (__bf16)x.x, b1 = (__bf16)x.y, b2 = (__bf16)x.z, b3 = (__bf16)x.w;
-        __bf16 *dst = center ? S.u.in.V + t * LD_V : S.u.in.T + t * LD_V;
-        dst[4 * q] = b0;
-        dst[4 * q + 1] = b1;
-        dst[4 * q + 2] = b2;
-        dst[4 * q + 3] = b3;
-        __bf16 *tr = center ? S.Vt + t : S.Tt + t;
-        const int ld = center ? LD_VT : LD_TT;
-        tr[(4 * q) * ld] = b0;
-        tr[(4 * q + 1) * ld] = b1;
-        tr[(4 * q + 2) * ld] = b2;
-        tr[(4 * q + 3) * ld] = b3;
+    // occurrences: every valid center row and target row once per walk
+    if (tid < SG_T) {
+        if ((uint32_t)tid < len) atomicAdd(A.cin + S.ids[tid], 1.f);
+        const bool tv = tid < SG_MAXC ? (uint32_t)tid < len : (uint32_t)(tid - SG_MAXC) < A.nneg;
+        if (tv) atomicAdd(A.cout + S.ids[tid], 1.f);
+    }
+    // rows to bf16 tiles, row-major and transposed: 32 lanes per row, 4 floats
+    // each; a thread's GATHER rows are loaded together, so their latencies
+    // overlap instead of adding up
+    constexpr int NROWS = SG_MAXC + SG_T;                // 256 rows
+    constexpr int RSTEP = SG_BLOCK / 32;                 // rows per pass of the block
+    constexpr int GATHER = 32;                           // loads in flight per thread (one batch)
+    static_assert(NROWS % (RSTEP * GATHER) == 0, "rows split evenly into gather batches");
+    const int q = tid & 31;
+    for (int r0 = tid / 32; r0 < NROWS; r0 += RSTEP * GATHER) {
+        float4 x[GATHER];
+#pragma unroll
+        for (int k = 0; k < GATHER; ++k) {
+            const int r = r0 + k * RSTEP;
+            const bool center = r < SG_MAXC;
+            const int t = center ? r : r - SG_MAXC;
+            const uint32_t id = S.ids[t];
+            const bool valid =
+                center ? (uint32_t)r < len : (t < SG_MAXC ? (uint32_t)t < len : (uint32_t)(t - SG_MAXC) < A.nneg);
+            x[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (valid) x[k] = *(const float4 *)((center ? A.win : A.wout) + (uint64_t)id * SG_DIM + 4 * q);
+        }
+#pragma unroll
+        for (int k = 0; k < GATHER; ++k) {
+            const int r = r0 + k * RSTEP;
+            const bool center = r < SG_MAXC;
+            const int t = center ? r : r - SG_MAXC;
+            const __bf16 b0 = (__bf16)x[k].x, b1 = (__bf16)x[k].y, b2 = (__bf16)x[k].z, b3 = (__bf16)x[k].w;
+            __bf16 *dst = center ? S.u.in.V + t * LD_V : S.u.in.T + t * LD_V;
+            dst[4 * q] = b0;
+            dst[4 * q + 1] = b1;
+            dst[4 * q + 2] = b2;
+            dst[4 * q + 3] = b3;
+            __bf16 *tr = center ? S.Vt + t : S.Tt + t;
+            const int ld = center ? LD_VT : LD_TT;
+            tr[(4 * q) * ld] = b0;
+            tr[(4 * q + 1) * ld] = b1;
+            tr[(4 * q + 2) * ld] = b2;
+            tr[(4 * q + 3) * ld] = b3;
+        }
     }
     __syncthreads();
     // logits: 3 x 5 tiles of 32 x 32, tile k of this wave is wv + 4k; gradient
@@ -216,20 +242,28 @@ __global__ __launch_bounds__(SG_BLOCK, 1) void k_sg_walks(SgArgs A)
     }
 }
 
-// w -= lr * g and g = 0 over a table (count floats, a multiple of 4).
-__global__ __launch_bounds__(256) void k_sg_apply(float *__restrict__ w, float *__restrict__ g, uint64_t count4,
-                                                  float lr)
+// w -= lr * g / max(1, c) and g = 0, c = 0 over a table of rows of SG_DIM
+// floats.  The 32 float4 of a row sit in one half of a wavefront (the stride
+// is a multiple of 64 threads), so every lane of the row reads c before its
+// first lane clears it.
+__global__ __launch_bounds__(256) void k_sg_apply(float *__restrict__ w, float *__restrict__ g, float *__restrict__ c,
+                                                  uint64_t count4, float lr)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count4; i += stride) {
+        const uint64_t row = i / (SG_DIM / 4);
+        const float occ = c[row];
+        const float s = lr / (occ > 1.f ? occ : 1.f);
         float4 a = ((float4 *)w)[i];
         const float4 b = ((float4 *)g)[i];
-        a.x -= lr * b.x;
-        a.y -= lr * b.y;
-        a.z -= lr * b.z;
-        a.w -= lr * b.w;
+        a.x -= s * b.x;
+        a.y -= s * b.y;
+        a.z -= s * b.z;
+        a.w -= s * b.w;
         ((float4 *)w)[i] = a;
         ((float4 *)g)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        __builtin_amdgcn_wave_barrier();
+        if ((i & (SG_DIM / 4 - 1)) == 0 && occ != 0.f) c[row] = 0.f;
     }
 }
 
@@ -255,6 +289,7 @@ __global__ __launch_bounds__(256) void k_sg_negatives(const uint64_t *__restrict
 
 struct SgLayout {
     float *gin, *gout;
+    float *cin, *cout;
     uint32_t *negs;
 };
 
@@ -263,6 +298,8 @@ size_t sg_layout(uint32_t n, uint32_t n_walks, uint32_t nneg, void *ws, size_t w
     Carver c(ws, ws_bytes);
     L->gin = c.take<float>((uint64_t)n * SG_DIM);
     L->gout = c.take<float>((uint64_t)n * SG_DIM);
+    L->cin = c.take<float>(n);
+    L->cout = c.take<float>(n);
     L->negs = c.take<uint32_t>((uint64_t)(n_walks ? n_walks : 1) * (nneg ? nneg : 1));
     return c.total();
 }
@@ -325,6 +362,8 @@ extern "C" int n2v_sgns_step(const n2v_sgns_params *prm, const uint32_t *walks, 
     A.wout = wout;
     A.gin = L.gin;
     A.gout = L.gout;
+    A.cin = L.cin;
+    A.cout = L.cout;
     A.loss = loss;
     A.n_walks = n_walks;
     A.row_len = row_len;
@@ -335,8 +374,8 @@ extern "C" int n2v_sgns_step(const n2v_sgns_params *prm, const uint32_t *walks, 
     N2V_HIP(hipGetLastError());
     const uint64_t count4 = (uint64_t)n * SG_DIM / 4;
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((count4 + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_sg_apply, dim3(blocks), dim3(256), 0, st, win, L.gin, count4, prm->lr);
-    hipLaunchKernelGGL(k_sg_apply, dim3(blocks), dim3(256), 0, st, wout, L.gout, count4, prm->lr);
+    hipLaunchKernelGGL(k_sg_apply, dim3(blocks), dim3(256), 0, st, win, L.gin, L.cin, count4, prm->lr);
+    hipLaunchKernelGGL(k_sg_apply, dim3(blocks), dim3(256), 0, st, wout, L.gout, L.cout, count4, prm->lr);
     N2V_HIP(hipGetLastError());
     return N2V_OK;
 }

@@ -571,7 +571,41 @@ __device__ __forceinline__ uint64_t seg_pi(const JobCtx &J, uint32_t pos_t, uint
 // Sketch row of the move at v from t (t at index pos_t of N(v)), or null.
 __device__ __forceinline__ uint16_t *sketch_row(const Exec &E, uint32_t v, uint32_t pos_t)
 {
-    return E.g.memo + (E.g.hbase[v] + pos_t) * (uint64_t)MEMO_ROW;
+    return E.g.memo + (E.g.hbase[v] + pos_t) * (uint64_t)memo_row_words(E.g.wt != nullptr);
+}
+
+// Weight sums of a tile whose flags are in LDS: all entries, flagged entries,
+// and both over the tile's first 256 entries (the runs of lanes 0..31).
+struct TileW {
+    uint32_t all, com, all1, com1;
+};
+
+__device__ __forceinline__ TileW tile_weights(const uint16_t *__restrict__ W, const HubLds &L, uint32_t j0, uint32_t cnt)
+{
+    const int l = lane_id();
+    const uint32_t i0 = (uint32_t)l * XPL;
+    const uint64_t f8 = *(const uint64_t *)&L.a.d.flag[i0];
+    uint32_t a = 0, c = 0;
+#pragma unroll
+    for (int e = 0; e < XPL; ++e) {
+        const uint32_t w = i0 + e < cnt ? W[j0 + i0 + e] : 0u;
+        a += w;
+        c += ((f8 >> (8 * e)) & 0xFF) ? w : 0u;
+    }
+    TileW t;
+    t.all = wave_sum32(a);
+    t.com = wave_sum32(c);
+    t.all1 = wave_sum32(l < WAVE / 2 ? a : 0u);
+    t.com1 = wave_sum32(l < WAVE / 2 ? c : 0u);
+    return t;
+}
+
+// pi summed over entries of a weighted row whose weights sum to wall, of which
+// members of N(t) sum to wcom, and t's own weight wt_t when t is among them
+// (A_ret for t, A_com for members, A_out for the rest).
+__device__ __forceinline__ uint64_t wseg_pi(const JobCtx &J, uint64_t wall, uint64_t wcom, uint64_t wt_t)
+{
+    return (uint64_t)J.A_out * (wall - wcom - wt_t) + (uint64_t)A_COM * wcom + (uint64_t)J.A_ret * wt_t;
 }
 
 // Reverse sketch to collect while merging a cold move at v (a hub) from t.
@@ -583,7 +617,8 @@ __device__ __forceinline__ uint16_t *rev_setup(const Exec &E, const WS &st, uint
     R.rc = rc;
     R.rh = rh;
     R.r1 = r1;
-    if (st.td < E.g.memo_min || st.td > MEMO_MAX_DEG) return nullptr;
+    // weighted rows need the weights of N(t), which a merge of N(v) does not read
+    if (E.g.wt || st.td < E.g.memo_min || st.td > MEMO_MAX_DEG) return nullptr;
     const uint32_t tsub = (st.td + TX - 1) / TX;
     const uint32_t tG = (tsub + NSUPER - 1) / NSUPER;
     R.rseg = tG * TX;
@@ -607,12 +642,17 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     const uint32_t seglen = G * TX;
     const uint32_t hs = hint_shift(td);
     uint16_t *row = nullptr;
-    if (E.g.memo && !W && pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) row = sketch_row(E, st.v, pos_t);
+    if (E.g.memo && pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) row = sketch_row(E, st.v, pos_t);
+    // weighted rows: per-segment weight sums after the u16 words (members of
+    // N(t) + 1, the same over the first half + 1, all entries, first half)
+    uint32_t *row32 = row && W ? (uint32_t *)(row + 3 * MEMO_SEGS) : nullptr;
+    const uint64_t wt_t = W && pos_t != SENT ? W[pos_t] : 0u;
     bool warm = false;
     // per segment (lane): count + 1; where its stream of N(t) may start (SENT:
     // unknown), and an index at or above that start; first-half count + 1 (0:
-    // unknown)
+    // unknown); weighted: the segment's weight sums (all, members; first half)
     uint32_t known = 1, ystart = SENT, ycap = td, halfv = 0, segcnt = 0;
+    uint32_t segw = 0, segcw = 0, segw1 = 0, segcw1 = 0;
     if (row) {
         if ((uint32_t)l < nsup) {
             known = row[l];
@@ -623,6 +663,17 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
                 const uint64_t up = (uint64_t)h << hs;
                 ycap = up < td ? (uint32_t)up : td;
             }
+            if (row32) {
+                // a word is 0 until written, and every writer writes the same
+                // value: a segment is known when all of its words are
+                const uint32_t cw = row32[l], cw1 = row32[MEMO_SEGS + l];
+                segw = row32[2 * MEMO_SEGS + l];
+                segw1 = row32[3 * MEMO_SEGS + l];
+                if (cw == 0 || segw == 0) known = 0;
+                if (cw1 == 0 || segw1 == 0) halfv = 0;
+                segcw = cw - 1;
+                segcw1 = cw1 - 1;
+            }
         }
         warm = ballot(known == 0) == 0;
     }
@@ -631,7 +682,9 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         uint64_t pi = 0;
         if ((uint32_t)l < nsup) {
             const uint32_t a = l * seglen;
-            pi = seg_pi(J, pos_t, a, dv - a < seglen ? dv - a : seglen, known - 1);
+            const uint32_t len = dv - a < seglen ? dv - a : seglen;
+            if (W) pi = wseg_pi(J, segw, segcw, pos_t >= a && pos_t - a < len ? wt_t : 0u);
+            else pi = seg_pi(J, pos_t, a, len, known - 1);
             L.b.csum[l] = pi;
         }
         S = wave_sum(pi);
@@ -655,6 +708,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         for (uint32_t sp = 0; sp < nsup; ++sp) {
             uint64_t sum = 0;
             uint32_t csp = 0, c1 = 0;  // members in the segment and in its first half
+            uint32_t sw = 0, scw = 0, sw1 = 0, scw1 = 0;  // weighted: the same as weight sums
             const uint32_t mid = sp * seglen + seglen / 2;
             if ((uint32_t)l == sp) ystart = ypos;
             const uint32_t sub_end = nsub < (sp + 1) * G ? nsub : (sp + 1) * G;
@@ -670,7 +724,16 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
                     c = dense_flags(X, Y, td, L, j0, cnt, ypos, R);
                 }
                 const uint32_t ct = c & 0xFFFFu;
-                sum += W ? dense_chunk_sum(W, J, pos_t, L, j0, cnt) : seg_pi(J, pos_t, j0, cnt, ct);
+                if (W) {
+                    const TileW tw = tile_weights(W, L, j0, cnt);
+                    sum += wseg_pi(J, tw.all, tw.com, pos_t >= j0 && pos_t - j0 < cnt ? wt_t : 0u);
+                    sw += tw.all;
+                    scw += tw.com;
+                    sw1 += j0 + cnt <= mid ? tw.all : (j0 < mid ? tw.all1 : 0u);
+                    scw1 += j0 + cnt <= mid ? tw.com : (j0 < mid ? tw.com1 : 0u);
+                } else {
+                    sum += seg_pi(J, pos_t, j0, cnt, ct);
+                }
                 csp += ct;
                 // the half boundary is a tile start or 256 entries into a tile
                 c1 += j0 + cnt <= mid ? ct : (j0 < mid ? c >> 16 : 0u);
@@ -680,7 +743,11 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             if ((uint32_t)l == sp) {
                 mine = csp;
                 segcnt = csp;
-                halfv = W ? 0u : c1 + 1;
+                halfv = c1 + 1;
+                segw = sw;
+                segcw = scw;
+                segw1 = sw1;
+                segcw1 = scw1;
             }
             S += sum;
         }
@@ -688,6 +755,12 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
             __builtin_nontemporal_store((uint16_t)((ystart >> hs) + 1), row + MEMO_SEGS + l);
             __builtin_nontemporal_store((uint16_t)halfv, row + 2 * MEMO_SEGS + l);
+            if (row32) {
+                __builtin_nontemporal_store(segcw + 1, row32 + l);
+                __builtin_nontemporal_store(segcw1 + 1, row32 + MEMO_SEGS + l);
+                __builtin_nontemporal_store(segw, row32 + 2 * MEMO_SEGS + l);
+                __builtin_nontemporal_store(segw1, row32 + 3 * MEMO_SEGS + l);
+            }
         }
         ycap = ystart;
         const uint32_t rsup = R.rseg ? (td + R.rseg - 1) / R.rseg : 0;
@@ -729,15 +802,17 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     const uint32_t hk = lane_val(halfv, (int)spx);
     const uint32_t segc = warm ? lane_val(known, (int)spx) - 1 : lane_val(segcnt, (int)spx);
     uint32_t crange = W ? SENT : segc;  // members of N(t) in [xa, xb), when known
-    if (hk != 0 && !W && mid < xe) {
-        const uint64_t p1 = seg_pi(J, pos_t, x0, mid - x0, hk - 1);
+    if (hk != 0 && mid < xe) {
+        const uint64_t p1 = W ? wseg_pi(J, lane_val(segw1, (int)spx), lane_val(segcw1, (int)spx),
+                                        pos_t >= x0 && pos_t < mid ? wt_t : 0u)
+                              : seg_pi(J, pos_t, x0, mid - x0, hk - 1);
         if (base + p1 > r) {
             xb = mid;
-            crange = hk - 1;
+            crange = W ? SENT : hk - 1;
         } else {
             base += p1;
             xa = mid;
-            crange = segc - (hk - 1);
+            crange = W ? SENT : segc - (hk - 1);
             if (crange != 0) ypos += wave_lower_bound(Y + ypos, yend - ypos, X[mid]);
         }
     }
@@ -1170,7 +1245,7 @@ __device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx
         return weighted_scan_locate(E, J, st, L, 1u, 0u, hi64(R1, E.g.wsum[st.v]));
     }
     bool sparse = use_sparse(E, st);
-    if (sparse && E.g.memo && !E.g.wt && st.pos_t != SENT && st.vd >= E.g.memo_min && st.vd <= MEMO_MAX_DEG) {
+    if (sparse && E.g.memo && st.pos_t != SENT && st.vd >= E.g.memo_min && st.vd <= MEMO_MAX_DEG) {
         // a sketch that an earlier move filled makes the dense path cheaper
         const uint32_t nsub = (st.vd + TX - 1) / TX;
         const uint32_t G = (nsub + NSUPER - 1) / NSUPER;
@@ -1550,7 +1625,7 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
                 // workgroups pay off on full merges: with sketches, only moves
                 // whose sketch looks unknown (first count still 0) go to them
                 big = s > 0 && st.vd > E.t_wg && !use_sparse(E, st) && !approx_first_order(E, S.c, st) &&
-                      !(E.g.memo && !E.g.wt && st.pos_t != SENT && st.vd >= E.g.memo_min &&
+                      !(E.g.memo && st.pos_t != SENT && st.vd >= E.g.memo_min &&
                         st.vd <= MEMO_MAX_DEG && sketch_row(E, st.v, st.pos_t)[0] != 0);
                 push = !big;
             } else {

@@ -64,3 +64,9 @@ def test_paper_context_names_the_papers_figures():
 def test_skew_profile_names_its_commands():
     txt = open(os.path.join(ROOT, "profiles", "k_persistent_skew5_kernel_trace.txt")).read()
     assert txt.count("rocprofv3 --kernel-trace --stats") == 2 and "--workload skew5 --approx 1000" in txt
+
+
+def test_output_line_is_strict_json():
+    # non-finite values are reported as null, never as NaN or Infinity
+    line = {"a": float("nan"), "b": [1.0, float("inf")], "c": {"d": -float("inf"), "e": 2}}
+    assert bench.finite(line) == {"a": None, "b": [1.0, None], "c": {"d": None, "e": 2}}

@@ -9,7 +9,7 @@ quarter of that, plus 2^-20 |g| for the fp32 exponential; the coefficient is
 rounded to bf16 again (u); each gradient element sum_t g_t x_t then errs by at
 most sum_t (dg_t + u |g_t|) |x_t| (1 + u) + (u + K 2^-24) sum_t |g_t x_t|, and
 the fp32 atomic sums over a row's contributions by 2^-20 of their absolute sum.
-The update w - lr g adds 2^-23 (|w| + lr |g|).
+The update w - (lr / occurrences) g adds 2^-23 (|w| + lr |g|).
 """
 import numpy as np
 import pytest
@@ -82,10 +82,12 @@ def run_case(og, walks, window, nneg, lr, seed, step, rng):
     torch.cuda.synchronize()
     gwin, gwout = sg.win.cpu().numpy(), sg.wout.cpu().numpy()
     gloss = float(sg.loss.cpu().numpy()[0])
-    owin, owout, oloss, ogin, ogout = SG.step(win, wout, walks, negs, window, lam, lr)
+    owin, owout, oloss, ogin, ogout, ocin, ocout = SG.step(win, wout, walks, negs, window, lam, lr)
     bi, bo, bl = bounds(win, wout, walks, negs, window, lam)
-    for got, want, b, g, w0, name in ((gwin, owin, bi, ogin, win, "win"), (gwout, owout, bo, ogout, wout, "wout")):
-        tol = lr * b + 2.0 ** -23 * (np.abs(w0) + lr * np.abs(g)) + 1e-12
+    for got, want, b, g, w0, occ, name in ((gwin, owin, bi, ogin, win, ocin, "win"),
+                                           (gwout, owout, bo, ogout, wout, ocout, "wout")):
+        s = (lr / np.maximum(occ, 1.0))[:, None]
+        tol = s * b + 2.0 ** -23 * (np.abs(w0) + s * np.abs(g)) + 1e-12
         err = np.abs(got.astype(np.float64) - want)
         worst = float((err / tol).max())
         touched = np.abs(g) > 0
@@ -130,8 +132,10 @@ def test_skipgram_two_steps_keep_the_workspace_clean():
     sg.step(wt, walk_base=0, step=1)
     torch.cuda.synchronize()
     negs = SG.negatives(noise_table(og), 9, 0, len(walks), 32, 1)
-    owin, owout, _, ogin, ogout = SG.step(win1, wout1, walks, negs, 4, sg.prm.neg_weight, 0.05)
+    owin, owout, _, ogin, ogout, ocin, ocout = SG.step(win1, wout1, walks, negs, 4, sg.prm.neg_weight, 0.05)
     bi, bo, _ = bounds(win1, wout1, walks, negs, 4, sg.prm.neg_weight)
-    for got, want, b, g, w0 in ((sg.win.cpu().numpy(), owin, bi, ogin, win1), (sg.wout.cpu().numpy(), owout, bo, ogout, wout1)):
-        tol = 0.05 * b + 2.0 ** -23 * (np.abs(w0) + 0.05 * np.abs(g)) + 1e-12
+    for got, want, b, g, w0, occ in ((sg.win.cpu().numpy(), owin, bi, ogin, win1, ocin),
+                                     (sg.wout.cpu().numpy(), owout, bo, ogout, wout1, ocout)):
+        s = (0.05 / np.maximum(occ, 1.0))[:, None]
+        tol = s * b + 2.0 ** -23 * (np.abs(w0) + s * np.abs(g)) + 1e-12
         assert (np.abs(got - want) <= tol).all()

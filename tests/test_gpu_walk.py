@@ -136,7 +136,7 @@ def test_workgroup_hub_class(weighted, memo):
     torch = torch_cuda()
     og = oracle_rmat(13, 16, *SKEW, 13, weighted)
     g = gpu_graph_from_oracle(og, d_rule=100)
-    if memo and not weighted:
+    if memo:
         g.attach_memo()
     deg = og.degree()
     hubs = np.argsort(deg)[-128:].astype(np.uint32)
@@ -148,9 +148,9 @@ def test_workgroup_hub_class(weighted, memo):
         got = gpu_walk(g, starts, 25, *pq, 31, mode=P.MODE_PLAIN, t_wg=t_wg, sparse_ratio=100000, memo=memo,
                        search_ratio=search)
         assert first_mismatch(got, want) is None, (t_wg, search, first_mismatch(got, want))
-    if memo and not weighted:
+    if memo:
         torch.cuda.synchronize()
-        n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192), 101)
+        n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 704 if weighted else 192), 101)
         assert n > 100
         g.detach_memo()
 
@@ -288,7 +288,9 @@ def check_sketch_rows(og, memo, min_deg, limit=6000, seed=1):
     hb = np.zeros(og.n + 1, dtype=np.int64)
     hb[1:] = np.cumsum(np.where(hub, deg, 0))
     rows = memo
-    assert rows.shape[0] >= hb[-1] and rows.shape[1] == 192
+    weighted = og.wt is not None
+    assert rows.shape[0] >= hb[-1] and rows.shape[1] == (704 if weighted else 192)
+    sums = np.ascontiguousarray(rows[:, 192:]).view(np.uint32) if weighted else None
     touched = np.nonzero(rows[:hb[-1]].any(axis=1))[0]
     rng = np.random.default_rng(seed)
     pick = touched if len(touched) <= limit else rng.choice(touched, limit, replace=False)
@@ -306,7 +308,21 @@ def check_sketch_rows(og, memo, min_deg, limit=6000, seed=1):
         want = np.add.reduceat(com.astype(np.int64), firsts) + 1
         got = rows[r, :64]
         assert np.array_equal(got[:nsup], want), (int(v), t, got[:nsup], want)
-        assert not got[nsup:].any() and not rows[r, 64 + nsup:128].any() and not rows[r, 128 + nsup:].any()
+        assert not got[nsup:].any() and not rows[r, 64 + nsup:128].any() and not rows[r, 128 + nsup:192].any()
+        if weighted:
+            # per segment: members' weight sum + 1, the same over the first half + 1, all
+            # entries' weight sum, the same over the first half (0 where not written)
+            w = og.wt[int(og.off[v]):int(og.off[v + 1])].astype(np.int64)
+            cw = np.add.reduceat(np.where(com, w, 0), firsts)
+            wa = np.add.reduceat(w, firsts)
+            cw1 = np.array([int(np.where(com, w, 0)[a:min(a + seglen // 2, len(nv))].sum()) for a in firsts])
+            wa1 = np.array([int(w[a:min(a + seglen // 2, len(nv))].sum()) for a in firsts])
+            sr = sums[r].astype(np.int64)
+            for k, want_k in ((0, cw + 1), (64, cw1 + 1), (128, wa), (192, wa1)):
+                part = sr[k:k + nsup]
+                assert np.all((part == 0) | (part == want_k)), (int(v), t, k)
+                assert not sr[k + nsup:k + 64].any()
+            assert np.all(sr[0:nsup] == cw + 1) and np.all(sr[128:128 + nsup] == wa)
         half = np.array([int(com[a:min(a + seglen // 2, len(nv))].sum()) for a in firsts]) + 1
         hv = rows[r, 128:128 + nsup].astype(np.int64)
         hknown = hv > 0
@@ -544,4 +560,28 @@ def test_sketches_persist_across_calls_and_clear(mode):
     assert int(torch.count_nonzero(g.memo).item()) == 0
     got = gpu_walk(g, starts, 20, 0.5, 2.0, 4, mode=mode)
     assert first_mismatch(got, oracle_walk(og, starts, 20, 0.5, 2.0, 4, d_rule=40)) is None
+    g.detach_memo()
+
+
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN])
+def test_weighted_pair_sketches(mode):
+    # weighted graphs keep sketches too (per-segment weight sums of the members of N(t) and of
+    # all entries beside the counts): walks over several calls, which read the rows the earlier
+    # ones wrote, equal the oracle's, and the rows hold exact sums
+    import torch
+    torch_cuda()
+    og = oracle_rmat(13, 16, *SKEW, 23, True)
+    g = gpu_graph_from_oracle(og, d_rule=40)
+    assert g.attach_memo() > 0
+    deg = og.degree()
+    hubs = np.argsort(deg)[-128:].astype(np.uint32)
+    starts = np.concatenate([np.repeat(hubs, 8), np.arange(og.n, dtype=np.uint32)])
+    say(f"[walk] weighted sketches mode={mode}")
+    for p, q, seed, opts in [(1.0, 0.5, 1, {}), (0.25, 4.0, 2, {"search_ratio": 0}), (2.0, 0.5, 3, {"sparse_ratio": 1})]:
+        got = gpu_walk(g, starts, 20, p, q, seed, mode=mode, **opts)
+        want = oracle_walk(og, starts, 20, p, q, seed, d_rule=40)
+        assert first_mismatch(got, want) is None, (p, q, first_mismatch(got, want))
+    torch.cuda.synchronize()
+    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 704), 41)
+    assert n > 100
     g.detach_memo()

@@ -242,6 +242,25 @@ def test_memo_pass_bytes_with_summaries_by_hand():
                      hub_moves=4, other_moves=1, intersections=1, warm_moves=1)
 
 
+def test_memo_pass_bytes_weighted_by_hand():
+    # the same rows, weighted: a summary row is 22 lines (four 32-bit sums per segment beside the
+    # 6 lines of counts and hints), the half segment's weights are read too, every key is
+    # directed (v, t), and building a summary costs the directed cold evaluation, weights of
+    # N(v) included (vertex 0: 100000 weights, 3125 lines; vertex 1: bytes 200000..205999 of
+    # wt, 94 lines).
+    off = np.array([0, 100000, 103000, 103001], dtype=np.uint64)
+    out = np.array([[2, 0, 1, 0, 1, 0]], dtype=np.uint32)
+    assert O.memo_warm_lines(off, 1, 0, weighted=True) == 22 + 64 + 32 + 2
+    # s = 1 at 0 after 2: summary 22 + 64 + 32 + 1 = 119 against cold min(6250 + 1, 1 + 13) + 3125
+    #   = 3139: 119, key (0, 2)
+    # s = 2 at 1 after 0: 22 + 16 + 8 + 534 = 580 against min(188 + 6250, 6250 + 800000) + 94
+    #   = 6532: 580, key (1, 0); s = 4 the same key again
+    # s = 3 at 0 after 1: 120 against min(6250 + 188, 188 + 39000) + 3125 = 9563: 120, key (0, 1)
+    hub = ((1 + 119) + (1 + 580) + (1 + 120) + (1 + 580)) * 64 + 4 * 4 + (3139 + 6532 + 9563) * 64
+    r = O.memo_pass_bytes(off, out, 5, d_rule=10, weighted=True)
+    assert r == dict(hub_bytes=hub, hub_moves=4, other_moves=1, intersections=3, warm_moves=4)
+
+
 def test_memo_model_is_below_the_isolated_model_on_repeated_pairs():
     # on a skewed R-MAT graph with four walks per vertex, hub pairs repeat: the memo-aware
     # bytes of the pass stay well below the isolated bytes of the same moves, and without

@@ -79,6 +79,10 @@ MUTATIONS = [
      "return lines_of(8, v, (uint64_t)v + 2);", "return lines_of(8, v, (uint64_t)v + 1);"),
     ("memo: search levels off by one",
      "while ((16ull << k) < d) ++k;", "while ((16ull << k) <= d) ++k;"),
+    ("memo: weighted summaries shared by both directions",
+     "if (!weighted && or_memo_keeps(dt, memo_min))", "if (or_memo_keeps(dt, memo_min))"),
+    ("memo: weighted summary row charged as unweighted",
+     "if (weighted) return 22 + (4 * h + 63) / 64", "if (weighted) return 6 + (4 * h + 63) / 64"),
     ("memo: summary read even when dearer",
      "            if (warm < cold) {", "            if (warm < cold + 1000000) {"),
     # the Skip-gram step that consumes the walks
@@ -94,6 +98,8 @@ MUTATIONS = [
      "np.where(pos, sigmoid(Z[:, :n]) - 1.0, 0.0)", "np.where(pos, 1.0 - sigmoid(Z[:, :n]), 0.0)", "skipgram.py"),
     ("sgns: target gradient from the wrong vectors",
      "np.add.at(gout, tids, G.T @ V)", "np.add.at(gout, tids, G.T @ (0.5 * V))", "skipgram.py"),
+    ("sgns: occurrences not counted per target",
+     "np.add.at(cout, tids, 1.0)", "cout[tids] += 1.0", "skipgram.py"),
 ]
 
 TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_rmat.py", "tests/test_oracle_law.py",

@@ -22,7 +22,7 @@ def test_gradient_is_the_derivative_of_the_loss():
     def loss(a, b):
         return SG.step(a, b, walks, negs, 2, 0.7, 0.0)[2]
 
-    _, _, L0, gin, gout = SG.step(win, wout, walks, negs, 2, 0.7, 0.0)
+    _, _, L0, gin, gout, cin, cout = SG.step(win, wout, walks, negs, 2, 0.7, 0.0)
     h = 1e-6
     for table, grad, which in ((win, gin, 0), (wout, gout, 1)):
         num = np.zeros_like(table)
@@ -34,10 +34,24 @@ def test_gradient_is_the_derivative_of_the_loss():
             lm = loss(b, wout) if which == 0 else loss(win, b)
             num[idx] = (lp - lm) / (2 * h)
         assert np.allclose(grad, num, rtol=1e-6, atol=1e-7), which
-    # the step moves against the gradient
-    nwin, nwout, _, _, _ = SG.step(win, wout, walks, negs, 2, 0.7, 0.1)
-    assert np.allclose(nwin, win - 0.1 * gin) and np.allclose(nwout, wout - 0.1 * gout)
+    # the step moves each row against its mean gradient per occurrence
+    nwin, nwout = SG.step(win, wout, walks, negs, 2, 0.7, 0.1)[:2]
+    assert np.allclose(nwin, win - 0.1 * gin / np.maximum(cin, 1)[:, None])
+    assert np.allclose(nwout, wout - 0.1 * gout / np.maximum(cout, 1)[:, None])
     assert loss(nwin, nwout) < L0
+
+
+def test_occurrences_by_hand():
+    # walk [0, 1, 0, 2], window 1, negatives (3, 3): vertex 0 is a center twice, 1 and 2 once;
+    # as targets 0 appears twice, 1 and 2 once, 3 twice (one per negative slot)
+    rng = np.random.default_rng(7)
+    win, wout = rng.normal(size=(4, 3)), rng.normal(size=(4, 3))
+    walks = np.array([[0, 1, 0, 2]], dtype=np.uint32)
+    negs = np.array([[3, 3]], dtype=np.uint32)
+    nwin, nwout, _, gin, gout, cin, cout = SG.step(win, wout, walks, negs, 1, 0.5, 0.2)
+    assert cin.tolist() == [2, 1, 1, 0] and cout.tolist() == [2, 1, 1, 2]
+    assert np.allclose(nwin[0], win[0] - 0.2 * gin[0] / 2) and np.allclose(nwin[3], win[3])
+    assert np.allclose(nwout[3], wout[3] - 0.2 * gout[3] / 2)
 
 
 def test_loss_at_zero_embeddings_counts_the_pairs():
@@ -46,7 +60,7 @@ def test_loss_at_zero_embeddings_counts_the_pairs():
     z = np.zeros((8, 4))
     walks = np.array([[1, 2, 3, 4, 5, S, S]], dtype=np.uint32)
     negs = np.array([[6, 7, 0]], dtype=np.uint32)
-    _, _, L, gin, gout = SG.step(z, z, walks, negs, 2, 0.25, 1.0)
+    _, _, L, gin, gout = SG.step(z, z, walks, negs, 2, 0.25, 1.0)[:5]
     assert math.isclose(L, math.log(2) * (14 + 0.25 * 15), rel_tol=1e-12)
     assert not gin.any() and not gout.any()  # zero vectors give zero gradients
 
@@ -58,7 +72,7 @@ def test_two_vertex_walk_by_hand():
     wout = np.array([[-0.5, 0.25], [2.0, 1.0]])
     walks = np.array([[0, 1]], dtype=np.uint32)
     negs = np.zeros((1, 0), dtype=np.uint32)
-    _, _, L, gin, gout = SG.step(win, wout, walks, negs, 1, 1.0, 0.0)
+    _, _, L, gin, gout = SG.step(win, wout, walks, negs, 1, 1.0, 0.0)[:5]
     z01 = 1.0 * 2.0 + 2.0 * 1.0      # v0 . u1 = 4
     z10 = 0.5 * -0.5 + -1.0 * 0.25   # v1 . u0 = -0.5
     sp = lambda x: math.log1p(math.exp(x))
