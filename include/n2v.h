@@ -133,8 +133,10 @@ int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const uint16_t *w
                      uint64_t m, const n2v_graph_opts *opts, void *ws, size_t ws_bytes,
                      void *stream, n2v_graph **out);
 
-/* Frees the handle (the caller's arrays and workspace stay the caller's).
- * N2V_EINVAL while a server created on the graph has not been destroyed. */
+/* Frees the handle (the caller's arrays and workspace stay the caller's),
+ * after waiting for replays of its recorded plain-form graphs still in
+ * flight.  N2V_EINVAL while a server created on the graph has not been
+ * destroyed. */
 int n2v_graph_destroy(n2v_graph *g);
 
 /* Number of vertices / entries and the rule parameters of a graph. */
@@ -189,7 +191,15 @@ int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_t L,
  * cnt[x] (device, n uint32) and H(walk id, c, x) to *checksum (device u64,
  * modulo 2^64), H = r0*2^32 + r1 of Philox(key = seed; ctr = (walk id mod
  * 2^32, c, x, 3)).  Counts accumulate: zero them before the first chunk.
- * `opts` may be NULL (defaults); `ws` may be NULL when the query says 0. */
+ * `opts` may be NULL (defaults); `ws` may be NULL when the query says 0.
+ * The plain form (N2V_MODE_PLAIN) is one superstep of two kernels per move
+ * (Algorithm 1).  A plain call whose every argument (pointers, sizes, options,
+ * seed) equals that of one of the graph's last 8 distinct plain calls is
+ * recorded into a HIP graph on its second occurrence and replayed from then
+ * on: one graph launch instead of 2L+2 kernel launches, same results, and the
+ * buffers' contents may change between calls.  Recording allocates the
+ * graph's host and device memory; calls enqueued on a stream that is being
+ * captured launch their kernels directly. */
 int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
                 uint32_t L, float p, float q, uint64_t seed, const n2v_exec_opts *opts,
                 int outputs, uint32_t *out, uint32_t *cnt, uint64_t *checksum, void *ws,

@@ -23,6 +23,7 @@
 // switches between thread and wave classes.
 #include <math.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <mutex>
@@ -47,6 +48,7 @@ struct WS {
     uint32_t td;     // degree of t
     uint32_t pos_t;  // index of t in N(v), SENT if absent
     uint32_t jprev;  // index of v in N(t)
+    uint64_t hb;     // first sketch row of v when loaded with v's record (hub moves), else ~0
 };
 
 namespace {
@@ -124,6 +126,7 @@ __device__ __forceinline__ WS bcast(const WS &s, int o)
     w.td = lane_val(s.td, o);
     w.pos_t = lane_val(s.pos_t, o);
     w.jprev = lane_val(s.jprev, o);
+    w.hb = lane_val64(s.hb, o);
     return w;
 }
 
@@ -146,9 +149,13 @@ __device__ __forceinline__ void emit(const JobCtx &J, uint32_t i, uint32_t col, 
     }
 }
 
+// v's record; a hub move also takes v's first sketch row in the same round
+// trip, which its sketch lookup would otherwise wait for
+template <bool HUB = false>
 __device__ __forceinline__ void load_v(const Exec &E, WS &st, uint32_t x)
 {
     const VRec r = E.g.vrec[x];
+    st.hb = HUB && E.g.memo ? E.g.hbase[x] : ~0ull;
     st.v = x;
     st.vo = r.off;
     st.vd = r.deg;
@@ -168,6 +175,7 @@ __device__ __forceinline__ void resolve(const Exec &E, const WS &st, uint32_t j,
     }
 }
 
+template <bool HUB = false>
 __device__ __forceinline__ void advance(const Exec &E, WS &st, uint32_t j, uint32_t x, uint32_t rev)
 {
     st.t = st.v;
@@ -175,7 +183,7 @@ __device__ __forceinline__ void advance(const Exec &E, WS &st, uint32_t j, uint3
     st.td = st.vd;
     st.jprev = j;
     st.pos_t = rev;
-    load_v(E, st, x);
+    load_v<HUB>(E, st, x);
     st.s += 1;
 }
 
@@ -574,6 +582,14 @@ __device__ __forceinline__ uint16_t *sketch_row(const Exec &E, uint32_t v, uint3
     return E.g.memo + (E.g.hbase[v] + pos_t) * (uint64_t)memo_row_words(E.g.wt != nullptr);
 }
 
+// The same for the move at st.v, from the first sketch row loaded with v's
+// record when there is one.
+__device__ __forceinline__ uint16_t *sketch_row(const Exec &E, const WS &st, uint32_t pos_t)
+{
+    const uint64_t hb = st.hb != ~0ull ? st.hb : E.g.hbase[st.v];
+    return E.g.memo + (hb + pos_t) * (uint64_t)memo_row_words(E.g.wt != nullptr);
+}
+
 // Weight sums of a tile whose flags are in LDS: all entries, flagged entries,
 // and both over the tile's first 256 entries (the runs of lanes 0..31).
 struct TileW {
@@ -642,7 +658,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     const uint32_t seglen = G * TX;
     const uint32_t hs = hint_shift(td);
     uint16_t *row = nullptr;
-    if (E.g.memo && pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) row = sketch_row(E, st.v, pos_t);
+    if (E.g.memo && pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) row = sketch_row(E, st, pos_t);
     // weighted rows: per-segment weight sums after the u16 words (members of
     // N(t) + 1, the same over the first half + 1, all entries, first half)
     uint32_t *row32 = row && W ? (uint32_t *)(row + 3 * MEMO_SEGS) : nullptr;
@@ -983,7 +999,7 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
         }
         wave_lds_sync();
         if ((uint32_t)l < nsup) {
-            uint16_t *row = sketch_row(E, st.v, st.pos_t);
+            uint16_t *row = sketch_row(E, st, st.pos_t);
             __builtin_nontemporal_store((uint16_t)(cnt[l] + 1), row + l);
             __builtin_nontemporal_store((uint16_t)(cnt1[l] + 1), row + 2 * MEMO_SEGS + l);
         }
@@ -1071,7 +1087,7 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
     const uint32_t seglen = G * TX;
     const uint32_t hs = hint_shift(td);
     uint16_t *row = nullptr;
-    if (E.g.memo && !W && pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) row = sketch_row(E, st.v, pos_t);
+    if (E.g.memo && !W && pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) row = sketch_row(E, st, pos_t);
     // one wavefront reads the sketch, so that the whole group takes one branch
     // even while another group is filling the same row
     if (wv == 0) {
@@ -1250,7 +1266,7 @@ __device__ __forceinline__ uint32_t wave_inverse_cdf(const Exec &E, const JobCtx
         const uint32_t nsub = (st.vd + TX - 1) / TX;
         const uint32_t G = (nsub + NSUPER - 1) / NSUPER;
         const uint32_t nsup = (nsub + G - 1) / G;
-        const uint16_t *row = sketch_row(E, st.v, st.pos_t);
+        const uint16_t *row = sketch_row(E, st, st.pos_t);
         const uint32_t known = (uint32_t)lane_id() < nsup ? row[lane_id()] : 1u;
         if (ballot(known == 0) == 0) sparse = false;
     }
@@ -1358,6 +1374,7 @@ struct Slot {
 };
 enum : uint32_t { SL_LIVE = 1, SL_PEND = 2, SL_CAP = 4 };
 
+template <bool HUB = false>
 __device__ __forceinline__ void slot_to_ws(const Exec &E, const Slot &q, WS &st)
 {
     st.job = q.job;
@@ -1366,7 +1383,7 @@ __device__ __forceinline__ void slot_to_ws(const Exec &E, const Slot &q, WS &st)
     st.t = q.t;
     st.pos_t = q.pos_t;
     st.jprev = q.jprev;
-    load_v(E, st, q.v);
+    load_v<HUB>(E, st, q.v);
     if (q.s > 0) {
         const VRec r = E.g.vrec[q.t];
         st.to = r.off;
@@ -1495,7 +1512,7 @@ __global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E, Src S)
             q.jprev = uni(sl[o].jprev);
             q.flags = uni(sl[o].flags);
             WS w;
-            slot_to_ws(E, q, w);
+            slot_to_ws<true>(E, q, w);
             w = uniform_ws(w);
             const JobCtx J = S.ctx(w.job);
             bool capped = q.flags & SL_CAP;
@@ -1521,7 +1538,7 @@ __global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E, Src S)
                 x = uni(x);
                 rev = uni(rev);
                 if (l == 0) emit<WALKS, COUNTS>(J, w.i, w.s + 1, x, csum);
-                advance(E, w, j, x, rev);
+                advance<true>(E, w, j, x, rev);
                 w = uniform_ws(w);
                 capped = false;
                 if (w.s == J.L || w.vd == 0) {
@@ -1565,13 +1582,14 @@ __global__ __launch_bounds__(256) void k_plain_init(Exec E, OneJob S, uint4 *__r
     }
 }
 
+template <bool HUB = false>
 __device__ __forceinline__ bool plain_load(const Exec &E, const uint4 &q, uint32_t i, uint32_t s, WS &st)
 {
     if (q.x == SENT) return false;
     st.job = 0;
     st.i = i;
     st.s = s;
-    load_v(E, st, q.x);
+    load_v<HUB>(E, st, q.x);
     st.t = q.y;
     st.pos_t = q.z;
     st.jprev = q.w;
@@ -1626,7 +1644,7 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
                 // whose sketch looks unknown (first count still 0) go to them
                 big = s > 0 && st.vd > E.t_wg && !use_sparse(E, st) && !approx_first_order(E, S.c, st) &&
                       !(E.g.memo && st.pos_t != SENT && st.vd >= E.g.memo_min &&
-                        st.vd <= MEMO_MAX_DEG && sketch_row(E, st.v, st.pos_t)[0] != 0);
+                        st.vd <= MEMO_MAX_DEG && sketch_row(E, st, st.pos_t)[0] != 0);
                 push = !big;
             } else {
                 uint32_t j;
@@ -1674,16 +1692,16 @@ __global__ __launch_bounds__(HBLOCK, 5) void k_plain_hub(Exec E, OneJob S, uint3
     HubLds &L = lds[threadIdx.x / WAVE];
     const bool lead = threadIdx.x < WAVE;
     uint64_t csum = 0;
+    // Each workgroup first takes the large move of its own index and each
+    // wavefront the small move of its own index; only the moves past those
+    // are claimed from the superstep's counters.  A short queue (the common
+    // case) then costs no atomics: thousands of claims on one counter would
+    // serialise in L2 and outlast the moves themselves.
     const uint32_t nb = *bign;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) blk.q = atomicAdd(bigd, 1u);
-        __syncthreads();
-        const uint32_t q = blk.q;
-        if (q >= nb) break;
+    for (uint32_t q = blockIdx.x; q < nb;) {
         const uint32_t i = uni(hubq[S.n - 1 - q]);
         WS st;
-        plain_load(E, state[i], i, s, st);
+        plain_load<true>(E, state[i], i, s, st);
         st = uniform_ws(st);
         const R4 rr = philox(S.c.k0, S.c.k1, S.c.wbase + st.i, st.s, 0u, 0u);
         uint32_t j = block_dense(E, S.c, st, L, blk, join64(rr.x, rr.y));
@@ -1694,26 +1712,37 @@ __global__ __launch_bounds__(HBLOCK, 5) void k_plain_hub(Exec E, OneJob S, uint3
             }
             plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, true);
         }
+        if (nb <= gridDim.x) break;
+        __syncthreads();
+        if (threadIdx.x == 0) blk.q = gridDim.x + atomicAdd(bigd, 1u);
+        __syncthreads();
+        q = blk.q;
     }
-    // wavefront moves, HUB_CLAIM per atomic (one counter serves the whole
-    // superstep, so single-move claims would serialise on it)
+    // wavefront moves past the first nwaves: up to HUB_CLAIM per atomic,
+    // sized so that what is left spreads over the grid
     const uint32_t n = *hubn;
-    for (;;) {
-        uint32_t q0 = 0;
-        if (lane_id() == 0) q0 = atomicAdd(hubd, (uint32_t)HUB_CLAIM);
-        q0 = uni(q0);
-        if (q0 >= n) break;
-        const uint32_t q1 = n - q0 < (uint32_t)HUB_CLAIM ? n : q0 + HUB_CLAIM;
+    const uint32_t nwaves = gridDim.x * (HBLOCK / WAVE);
+    const uint32_t rest = n > nwaves ? n - nwaves : 0u;
+    const uint32_t per = (rest + nwaves - 1) / nwaves;
+    const uint32_t claim = per < 1u ? 1u : (per > (uint32_t)HUB_CLAIM ? (uint32_t)HUB_CLAIM : per);
+    uint32_t q0 = blockIdx.x * (HBLOCK / WAVE) + threadIdx.x / WAVE, q1 = q0 + 1;
+    while (q0 < n) {
+        if (q1 > n) q1 = n;
         for (uint32_t q = q0; q < q1; ++q) {
             const uint32_t item = uni(hubq[q]);
             const uint32_t i = item & 0x7FFFFFFFu;
             const uint32_t kidx = (item & 0x80000000u) ? E.g.a_cap : 0u;
             WS st;
-            plain_load(E, state[i], i, s, st);
+            plain_load<true>(E, state[i], i, s, st);
             uint32_t xj;
             const uint32_t j = wave_inverse_cdf(E, S.c, st, kidx, L, xj);
             plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, true);
         }
+        if (rest == 0) break;
+        uint32_t b = 0;
+        if (lane_id() == 0) b = atomicAdd(hubd, claim);
+        q0 = nwaves + uni(b);
+        q1 = q0 + claim;
     }
     if (COUNTS) {
         csum = wave_sum(csum);
@@ -1833,11 +1862,52 @@ int walk_multipliers(float p, float q, uint32_t *A_ret, uint32_t *A_out)
 // Walk counters of a graph: a persistent launch takes a counter slot that no
 // launch still in flight holds (an event recorded after each launch tells),
 // so overlapping calls never share a counter.
+//
+// The same host record keeps the graph's captured plain-form launch
+// sequences.  The plain form issues 2L+2 kernels per call.  A call whose
+// every launch argument (graph view, options, job, starts, outputs,
+// workspace, grid) equals that of one of the last PLAIN_GRAPHS distinct calls
+// is recorded into a hipGraph on its second occurrence and replayed from then
+// on: one graph launch instead of 2L+2 kernel launches.  A replay runs exactly
+// the kernels, grids and arguments of the direct launches, so results are the
+// same; the contents of the buffers may change between calls.
+constexpr int PLAIN_GRAPHS = 8;
+constexpr int PLAIN_KEY_WORDS = 32;
+
+struct PlainKey {
+    uint64_t w[PLAIN_KEY_WORDS] = {};
+    int n = 0;
+    void put(uint64_t x) { w[n++] = x; }
+    void put(const void *p) { put((uint64_t)(uintptr_t)p); }
+    void put2(uint32_t hi, uint32_t lo) { put(((uint64_t)hi << 32) | lo); }
+    bool operator==(const PlainKey &o) const { return n == o.n && !memcmp(w, o.w, sizeof(uint64_t) * n); }
+};
+
+struct PlainGraph {
+    PlainKey key;                   // n == 0: unused
+    hipGraphExec_t exec = nullptr;  // null: seen once, not captured yet
+    hipEvent_t done = nullptr;      // recorded after each replay
+    uint64_t used = 0;              // last use (LRU)
+};
+
 struct CursorSlots {
     std::mutex mu;
     hipEvent_t ev[CURSOR_SLOTS] = {};
     int next = 0;
+    PlainGraph plain[PLAIN_GRAPHS];
+    uint64_t clock = 0;
+    hipStream_t cap = nullptr;  // private stream the plain form is captured on
 };
+
+void plain_graph_drop(PlainGraph &e)
+{
+    if (e.done) {
+        (void)hipEventSynchronize(e.done);
+        (void)hipEventDestroy(e.done);
+    }
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    e = PlainGraph();
+}
 
 void *cursor_slots_new() { return new (std::nothrow) CursorSlots(); }
 
@@ -1847,6 +1917,8 @@ void cursor_slots_free(void *p)
     if (!cs) return;
     for (hipEvent_t &e : cs->ev)
         if (e) (void)hipEventDestroy(e);
+    for (PlainGraph &e : cs->plain) plain_graph_drop(e);
+    if (cs->cap) (void)hipStreamDestroy(cs->cap);
     delete cs;
 }
 
@@ -1883,6 +1955,120 @@ void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E)
     E->t_wg = o.t_wg < g->dg.d_rule ? g->dg.d_rule : o.t_wg;
     E->search_ratio = o.search_ratio;
     E->sparse_ratio = o.sparse_ratio < 1 ? 1 : o.sparse_ratio;
+}
+
+PlainKey plain_key(const Exec &E, const OneJob &S, const void *ws, uint32_t hub_blocks, bool W, bool C)
+{
+    // every field the launches read from the host: a new field of Exec,
+    // DevGraph, JobCtx or OneJob must be added here
+    static_assert(sizeof(DevGraph) == 112 && sizeof(Exec) == 144 && sizeof(JobCtx) == 56 && sizeof(OneJob) == 80,
+                  "plain_key covers every launch argument");
+    PlainKey k;
+    const DevGraph &d = E.g;
+    k.put(d.vrec);
+    k.put(d.erec);
+    k.put(d.adj);
+    k.put(d.wt);
+    k.put(d.wsum);
+    k.put(d.hbase);
+    k.put(d.memo);
+    k.put(d.status);
+    k.put(d.cursors);
+    k.put2(d.n, d.d_rule);
+    k.put(d.m);
+    k.put2(d.memo_min, d.a_cap);
+    k.put2(d.wlo, d.whi);
+    k.put2(E.t_wave, E.t_sparse);
+    k.put2(E.sparse_ratio, E.t_wg);
+    k.put2(E.search_ratio, hub_blocks);
+    k.put(E.cursor);
+    k.put(S.c.out);
+    k.put(S.c.cnt);
+    k.put(S.c.checksum);
+    k.put2(S.c.wbase, S.c.L);
+    k.put2(S.c.k0, S.c.k1);
+    k.put2(S.c.A_ret, S.c.A_out);
+    k.put2(S.c.approx_t, S.n);
+    k.put(S.starts);
+    k.put(S.cur);
+    k.put(ws);
+    k.put((W ? 1u : 0u) | (C ? 2u : 0u));
+    return k;
+}
+
+template <bool W, bool C>
+int capture_plain(CursorSlots *cs, const Exec &E, const OneJob &S, void *ws, int dev, hipGraphExec_t *out)
+{
+    if (!cs->cap) N2V_HIP(hipStreamCreateWithFlags(&cs->cap, hipStreamNonBlocking));
+    N2V_HIP(hipStreamBeginCapture(cs->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = launch_plain<W, C>(E, S, ws, dev, cs->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs->cap, &graph);
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc ? rc : hip_fail(e, "hipStreamEndCapture (plain form)");
+    }
+    const hipError_t e2 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+        *out = nullptr;
+        return hip_fail(e2, "hipGraphInstantiate (plain form)");
+    }
+    return N2V_OK;
+}
+
+// The plain form, direct or replayed from a captured graph (see PlainGraph).
+// Calls enqueued on a stream that is itself being captured launch directly.
+template <bool W, bool C>
+int launch_plain_replayed(const n2v_graph *g, const Exec &E, const OneJob &S, void *ws, hipStream_t st)
+{
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = hipStreamCaptureStatusActive;  // unknown: do not capture
+    }
+    if (cap != hipStreamCaptureStatusNone) return launch_plain<W, C>(E, S, ws, g->device, st);
+    const PlainKey k = plain_key(E, S, ws, (uint32_t)dev_info(g->device).cus * 8, W, C);
+    CursorSlots *cs = (CursorSlots *)g->slots;
+    std::lock_guard<std::mutex> lk(cs->mu);
+    const uint64_t now = ++cs->clock;
+    PlainGraph *hit = nullptr;
+    for (PlainGraph &e : cs->plain)
+        if (e.key.n && e.key == k) hit = &e;
+    if (!hit) {
+        // first occurrence: remember it in the least recently used entry that
+        // no replay in flight holds, and launch directly
+        PlainGraph *victim = nullptr;
+        for (PlainGraph &e : cs->plain) {
+            if (e.done) {
+                const hipError_t q = hipEventQuery(e.done);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) return hip_fail(q, "hipEventQuery (plain form graph)");
+            }
+            if (!victim || e.used < victim->used) victim = &e;
+        }
+        if (victim) {
+            plain_graph_drop(*victim);
+            victim->key = k;
+            victim->used = now;
+        }
+        return launch_plain<W, C>(E, S, ws, g->device, st);
+    }
+    hit->used = now;
+    if (!hit->exec) {
+        int rc = capture_plain<W, C>(cs, E, S, ws, g->device, &hit->exec);
+        if (rc == N2V_OK && !hit->done) {
+            const hipError_t e = hipEventCreateWithFlags(&hit->done, hipEventDisableTiming);
+            if (e != hipSuccess) rc = hip_fail(e, "hipEventCreate (plain form graph)");
+        }
+        if (rc) {
+            plain_graph_drop(*hit);
+            return rc;
+        }
+    }
+    N2V_HIP(hipGraphLaunch(hit->exec, st));
+    N2V_HIP(hipEventRecord(hit->done, st));
+    return N2V_OK;
 }
 
 uint32_t full_grid_blocks(int dev)
@@ -1946,10 +2132,15 @@ extern "C" int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_
     return N2V_OK;
 }
 
-extern "C" int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
-                               uint32_t L, float p, float q, uint64_t seed, uint32_t approx_t,
-                               const n2v_exec_opts *opts, int outputs, uint32_t *out, uint32_t *cnt,
-                               uint64_t *checksum, void *ws, size_t ws_bytes, void *stream)
+namespace n2v {
+namespace {
+
+// Every walk entry point: `replay` lets the plain form use captured graphs
+// (instantiating one allocates, so the static entry point launches directly).
+int walk_impl(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base, uint32_t L,
+              float p, float q, uint64_t seed, uint32_t approx_t, const n2v_exec_opts *opts, int outputs,
+              uint32_t *out, uint32_t *cnt, uint64_t *checksum, void *ws, size_t ws_bytes, void *stream,
+              bool replay)
 {
     if (!g) return set_error(N2V_EINVAL, "n2v_walk: null graph");
     if (L < 1) return set_error(N2V_EINVAL, "n2v_walk: L must be >= 1");
@@ -1991,6 +2182,11 @@ extern "C" int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint3
         const size_t need = plain_ws(n_starts, L);
         if (!ws || ws_bytes < need) return set_error(N2V_ENOMEM, "n2v_walk: plain form needs %zu workspace bytes", need);
         if (((uintptr_t)ws & 255) != 0) return set_error(N2V_EINVAL, "n2v_walk: workspace not 256-byte aligned");
+        if (replay) {
+            if (W && C) return launch_plain_replayed<true, true>(g, E, S, ws, st);
+            if (W) return launch_plain_replayed<true, false>(g, E, S, ws, st);
+            return launch_plain_replayed<false, true>(g, E, S, ws, st);
+        }
         if (W && C) return launch_plain<true, true>(E, S, ws, g->device, st);
         if (W) return launch_plain<true, false>(E, S, ws, g->device, st);
         return launch_plain<false, true>(E, S, ws, g->device, st);
@@ -2001,6 +2197,18 @@ extern "C" int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint3
         if (W) return launch_persistent<true, false>(E, S, o, g->device, st);
         return launch_persistent<false, true>(E, S, o, g->device, st);
     });
+}
+
+}  // namespace
+}  // namespace n2v
+
+extern "C" int n2v_walk_approx(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
+                               uint32_t L, float p, float q, uint64_t seed, uint32_t approx_t,
+                               const n2v_exec_opts *opts, int outputs, uint32_t *out, uint32_t *cnt,
+                               uint64_t *checksum, void *ws, size_t ws_bytes, void *stream)
+{
+    return walk_impl(g, starts, n_starts, walk_base, L, p, q, seed, approx_t, opts, outputs, out, cnt, checksum, ws,
+                     ws_bytes, stream, true);
 }
 
 extern "C" int n2v_walk_ex(const n2v_graph *g, const uint32_t *starts, uint32_t n_starts, uint64_t walk_base,
@@ -2087,6 +2295,6 @@ extern "C" int n2v_walk_static(const n2v_graph *g, const uint32_t *starts, uint3
     n2v_exec_opts_default(g, &o);
     if (opts) o = *opts;
     o.mode = N2V_MODE_PLAIN;
-    return n2v_walk_approx(g, starts, n_starts, walk_base, L, p, q, seed, approx_t, &o, outputs, out, cnt, checksum,
-                           ws, STATIC_SCRATCH_BYTES, stream);
+    return walk_impl(g, starts, n_starts, walk_base, L, p, q, seed, approx_t, &o, outputs, out, cnt, checksum, ws,
+                     STATIC_SCRATCH_BYTES, stream, false);
 }

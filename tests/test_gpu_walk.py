@@ -585,3 +585,53 @@ def test_weighted_pair_sketches(mode):
     n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 704), 41)
     assert n > 100
     g.detach_memo()
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_plain_form_graph_replays(weighted):
+    # a plain-form call whose arguments repeat is captured on its second
+    # occurrence and replayed afterwards: every call, direct, capturing or
+    # replayed, must match the oracle, also after the buffers' contents change,
+    # on another stream, and after more distinct calls than the graph keeps
+    torch = torch_cuda()
+    og = oracle_rmat(12, 16, *SKEW, 21, weighted)
+    g = gpu_graph_from_oracle(og, d_rule=64)
+    g.attach_memo()
+    pq = (1.0, 0.5) if weighted else (0.25, 4.0)
+    L = 30
+    opts = P.exec_opts(g, mode=P.MODE_PLAIN, t_wg=200)
+    starts_a = np.tile(np.arange(og.n, dtype=np.uint32), 2)
+    starts_b = np.random.default_rng(5).integers(0, og.n, len(starts_a)).astype(np.uint32)
+    n = len(starts_a)
+    st = starts_tensor(torch, starts_a)
+    out = torch.empty((n, L + 1), dtype=torch.int32, device="cuda")
+    ws = P._alloc(g.walk_workspace(n, L, opts), "cuda")
+    side = torch.cuda.Stream()
+    seeds = list(range(40, 50))  # more distinct calls than the graph keeps captured
+    want = {(k, s): oracle_walk(og, src, L, *pq, s, d_rule=64)
+            for k, src in (("a", starts_a), ("b", starts_b)) for s in seeds[:2]}
+    plan = [("a", seeds[0])] * 3 + [("b", seeds[0])] * 2 + [("a", seeds[1])] * 2
+    plan += [("a", s) for s in seeds for _ in range(2)] + [("b", seeds[1]), ("a", seeds[0])] * 2
+    for k, (src, seed) in enumerate(plan):
+        say(f"[walk] plain replay call {k}: starts {src} seed {seed} weighted={weighted}")
+        stream = side if k % 3 == 2 else torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        st.copy_(torch.from_numpy((starts_a if src == "a" else starts_b).view(np.int32)))
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        g.walk(st, L, *pq, seed, out=out, opts=opts, ws=ws, stream=stream)
+        torch.cuda.synchronize()
+        ref = want.get((src, seed))
+        if ref is None:
+            ref = want[(src, seed)] = oracle_walk(og, starts_a if src == "a" else starts_b, L, *pq, seed, d_rule=64)
+        assert first_mismatch(u32(out), ref) is None, (k, src, seed, first_mismatch(u32(out), ref))
+    # counts replayed the same way accumulate like direct calls
+    cnt = torch.zeros(og.n, dtype=torch.int32, device="cuda")
+    cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st.copy_(torch.from_numpy(starts_a.view(np.int32)))
+    for _ in range(3):
+        g.walk_counts(st, L, *pq, seeds[0], cnt, cs, opts=opts, ws=ws)
+    torch.cuda.synchronize()
+    ref = O.walk(og, starts_a, L, *pq, seeds[0], d_rule=64, want_counts=True, nthreads=16)
+    assert np.array_equal(u32(cnt), 3 * ref["cnt"].astype(np.uint32))
+    assert int(cs.cpu().numpy().view(np.uint64)[0]) == (3 * ref["checksum"]) % (1 << 64)
