@@ -1045,6 +1045,10 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
 __device__ __forceinline__ bool use_sparse(const Exec &E, const WS &st)
 {
     if (st.td + 1 > (uint32_t)SPCAP || st.td > E.t_sparse) return false;
+    // on a weighted graph the sparse path locates the entry by scanning N(v)'s
+    // weights; a move that keeps a pair sketch takes the dense path instead,
+    // which fills the sketch, so that later visits recompute half a segment
+    if (E.g.wt && E.g.memo && st.pos_t != SENT && st.vd >= E.g.memo_min && st.vd <= MEMO_MAX_DEG) return false;
     const uint32_t lg = 32 - __clz(st.vd);
     return (uint64_t)st.td * E.sparse_ratio * lg < (uint64_t)st.vd + st.td;
 }
