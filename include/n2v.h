@@ -164,7 +164,7 @@ typedef struct {
                             wavefront each (default 65536) */
     uint32_t search_ratio; /* dense hub moves look N(v)'s entries up in N(t) (pivots in LDS, then
                             a search in one bucket) instead of streaming N(t) when the part of
-                            N(t) to stream is more than search_ratio times longer (default 8;
+                            N(t) to stream is more than search_ratio times longer (default 24;
                             0: always look up) */
 } n2v_exec_opts;
 

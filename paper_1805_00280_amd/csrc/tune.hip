@@ -119,12 +119,13 @@ extern "C" int n2v_autotune(n2v_graph *g, uint32_t n_walks, uint32_t L, float p,
     int rc = run(cur, &cur_ms);
     if (rc) return rc;
     const uint32_t t_wave_c[] = {0, 8, 32, 64, 128, 256, 1024};
-    const uint32_t ratio_c[] = {2, 4, 8, 16, 32};
+    // sparse_ratio 2^20 keeps every hub move on the dense path
+    const uint32_t ratio_c[] = {1, 2, 4, 8, 16, 32, 1u << 20};
     const uint32_t waves_c[] = {0, 8, 12, 16};
-    const uint32_t search_c[] = {0, 1, 2, 4, 16, 0xFFFFFFFFu};
+    const uint32_t search_c[] = {0, 2, 4, 8, 16, 64, 0xFFFFFFFFu};
     for (int pass = 0; pass < 4; ++pass) {
         const uint32_t *vals = pass == 0 ? t_wave_c : pass == 1 ? ratio_c : pass == 2 ? waves_c : search_c;
-        const int nv = pass == 0 ? 7 : pass == 1 ? 5 : pass == 2 ? 4 : 6;
+        const int nv = pass == 0 ? 7 : pass == 1 ? 7 : pass == 2 ? 4 : 7;
         for (int i = 0; i < nv; ++i) {
             n2v_exec_opts o = cur;
             if (pass == 0) o.t_wave = vals[i];

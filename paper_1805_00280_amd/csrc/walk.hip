@@ -1615,16 +1615,9 @@ __device__ __forceinline__ void plain_finish(const Exec &E, const JobCtx &J, WS 
     uint32_t x, rev;
     resolve(E, st, j, x, rev);
     if (!wave || lane_id() == 0) emit<WALKS, COUNTS>(J, st.i, st.s + 1, x, csum);
-    const uint32_t s1 = st.s + 1;
-    bool end = s1 == J.L;
-    if (!end) {
-        const VRec r = E.g.vrec[x];
-        if (r.deg == 0) {
-            end = true;
-            if (wave) fill_tail_wave<WALKS>(J, st.i, s1);
-            else fill_tail_lane<WALKS>(J, st.i, s1);
-        }
-    }
+    // a dead end at x is found by the next superstep, which loads x's record
+    // anyway
+    const bool end = st.s + 1 == J.L;
     if (!wave || lane_id() == 0) state[st.i] = make_uint4(end ? SENT : x, st.v, rev, j);
 }
 
@@ -1642,7 +1635,11 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
     if (i < S.n) {
         WS st;
         if (plain_load(E, state[i], i, s, st)) {
-            if (st.vd > E.g.d_rule) {
+            if (st.vd == 0) {
+                // the previous move reached a dead end: the rest of the row is N2V_SENT
+                fill_tail_lane<WALKS>(S.c, i, s);
+                state[i].x = SENT;
+            } else if (st.vd > E.g.d_rule) {
                 item = i;
                 // workgroups pay off on full merges: with sketches, only moves
                 // whose sketch looks unknown (first count still 0) go to them
@@ -1835,8 +1832,12 @@ int launch_plain(const Exec &E, const OneJob &S, void *ws, int dev, hipStream_t 
     N2V_HIP(hipGetLastError());
     DevInfo &d = dev_info(dev);
     const uint32_t hub_blocks = (uint32_t)d.cus * 8;
+    // the thread kernel lasts as long as its slowest lane's chain of dependent
+    // reads: a small superstep is spread over every CU, one wavefront per block
+    const uint32_t tpb = S.n < (uint32_t)d.cus * 1024u ? 64u : 256u;
+    const uint32_t sblocks = (S.n + tpb - 1) / tpb;
     for (uint32_t s = 0; s < S.c.L; ++s) {
-        hipLaunchKernelGGL((k_plain_step<W, C>), dim3(blocks), dim3(256), 0, st, E, S, s, state, hubq, hubn + s,
+        hipLaunchKernelGGL((k_plain_step<W, C>), dim3(sblocks), dim3(tpb), 0, st, E, S, s, state, hubq, hubn + s,
                            bign + s);
         hipLaunchKernelGGL((k_plain_hub<W, C>), dim3(hub_blocks), dim3(HBLOCK), 0, st, E, S, s, state, hubq,
                            (const uint32_t *)(hubn + s), hubd + s, (const uint32_t *)(bign + s), bigd + s);
@@ -2122,7 +2123,7 @@ extern "C" void n2v_exec_opts_default(const n2v_graph *g, n2v_exec_opts *o)
     o->block = 256;
     o->memo = 1;
     o->t_wg = 65536;
-    o->search_ratio = 8;
+    o->search_ratio = 24;
 }
 
 extern "C" int n2v_walk_workspace(const n2v_graph *g, uint32_t n_starts, uint32_t L, const n2v_exec_opts *opts,

@@ -42,7 +42,7 @@ def test_defaults(lib):
     assert (g.d_rule, g.a_cap, g.validate) == (1024, 1024, 1)
     o = P.exec_opts()
     assert o.mode == P.MODE_AUTO and o.t_wave <= 1024
-    assert o.memo == 1 and o.t_wg == 65536 and o.search_ratio == 8
+    assert o.memo == 1 and o.t_wg == 65536 and o.search_ratio == 24
     s = P.ServerOpts()
     lib.n2v_server_opts_default(C.byref(s))
     assert s.chunk_walks > 0 and s.max_queue > 0

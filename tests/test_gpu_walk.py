@@ -189,12 +189,31 @@ def test_edge_cases(c1):
         g.walk(starts_tensor(torch, starts), 5, 0.3, 1.0, 1)
 
 
-def test_directed_dead_end_and_tiny_graphs():
+@pytest.mark.parametrize("mode", [P.MODE_PERSISTENT, P.MODE_PLAIN, "plain_wg"])
+def test_directed_dead_end_and_tiny_graphs(mode):
+    # dead ends reached by thread moves (d_rule 1024) and by hub moves (d_rule 0)
+    kw = dict(mode=P.MODE_PLAIN, t_wg=0) if mode == "plain_wg" else dict(mode=mode)
     torch_cuda()
     g = O.CSR(np.array([0, 1, 2, 2], dtype=np.uint64), np.array([1, 2], dtype=np.uint32))
-    gg = gpu_graph_from_oracle(g)
-    got = gpu_walk(gg, np.array([0, 1, 2], dtype=np.uint32), 5, 1.0, 1.0, 1)
-    assert first_mismatch(got, oracle_walk(g, np.array([0, 1, 2], dtype=np.uint32), 5, 1.0, 1.0, 1)) is None
+    for d_rule in (0, 1024):
+        gg = gpu_graph_from_oracle(g, d_rule=d_rule)
+        st3 = np.tile(np.array([0, 1, 2], dtype=np.uint32), 7)
+        got = gpu_walk(gg, st3, 5, 1.0, 1.0, 1, **kw)
+        assert first_mismatch(got, oracle_walk(g, st3, 5, 1.0, 1.0, 1, d_rule=d_rule)) is None, d_rule
+    # a directed graph whose hubs lead into sinks: walks end at every superstep
+    rng = np.random.default_rng(3)
+    edges = sorted({(int(a), int(b)) for a, b in zip(rng.integers(0, 24, 1500), rng.integers(0, 40, 1500)) if a != b})
+    off = np.zeros(41, dtype=np.uint64)
+    for a, _ in edges:
+        off[a + 1] += 1
+    og = O.CSR(np.cumsum(off).astype(np.uint64), np.array([b for _, b in edges], dtype=np.uint32))
+    for d_rule in (0, 32):
+        gg = gpu_graph_from_oracle(og, d_rule=d_rule)
+        starts = np.tile(np.arange(24, dtype=np.uint32), 40)
+        want = oracle_walk(og, starts, 12, 0.5, 2.0, 9, d_rule=d_rule)
+        assert (want == 0xFFFFFFFF).any()
+        got = gpu_walk(gg, starts, 12, 0.5, 2.0, 9, **kw)
+        assert first_mismatch(got, want) is None, (d_rule, first_mismatch(got, want))
     for edges, n in [([(0, 1)], 2), ([(0, i) for i in range(1, 40)], 40),
                      ([(a, b) for a in range(12) for b in range(a + 1, 12)], 12)]:
         og = O.CSR.from_edges(n, edges)
@@ -202,7 +221,7 @@ def test_directed_dead_end_and_tiny_graphs():
             gg = gpu_graph_from_oracle(og, d_rule=d_rule)
             starts = np.tile(np.arange(n, dtype=np.uint32), 30)
             want = oracle_walk(og, starts, 15, 0.25, 4.0, 6, d_rule=d_rule)
-            got = gpu_walk(gg, starts, 15, 0.25, 4.0, 6)
+            got = gpu_walk(gg, starts, 15, 0.25, 4.0, 6, **kw)
             assert first_mismatch(got, want) is None, (n, d_rule, first_mismatch(got, want))
 
 
