@@ -33,7 +33,7 @@ def test_measured_traffic_is_used_only_for_the_profiled_kernel(monkeypatch):
     t = json.load(open(os.path.join(ROOT, "profiles", f"traffic_{name}.json")))
     assert t["bytes_per_launch"] == t["fetch_bytes"] + t["write_bytes"] > 0
     monkeypatch.setattr(bench, "kernel_sha", lambda: t["kernel_sha"])
-    assert bench.load_traffic(name) == t["bytes_per_launch"]
+    assert bench.load_traffic(name)["bytes_per_launch"] == t["bytes_per_launch"]
     monkeypatch.setattr(bench, "kernel_sha", lambda: "0" * 16)
     assert bench.load_traffic(name) is None
     assert bench.load_traffic("no-such-workload") is None
