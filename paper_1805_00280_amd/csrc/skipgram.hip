@@ -16,8 +16,8 @@
 //   - after every walk of the batch is evaluated against the same tables, both
 //     tables take one SGD step in which each row moves by its mean gradient
 //     per occurrence in the batch: w -= lr * gradient / occurrences.
-// Per walk the three contractions (logits, center gradients, target
-// gradients) are dense products of at most 96 centers by 160 targets by 128
+// Per walk the contractions (logits, center gradients, target gradients)
+// are dense products of at most 96 centers by 160 targets by 128
 // dimensions; one workgroup evaluates them with bf16 MFMA (fp32 accumulate)
 // from LDS tiles, and adds the gradient rows into fp32 gradient tables.
 #include <math.h>
@@ -35,11 +35,9 @@ constexpr int SG_MAXC = 96;               // walk positions per walk (L + 1 <= 9
 constexpr int SG_MAXNEG = 64;             // shared negatives per walk
 constexpr int SG_T = SG_MAXC + SG_MAXNEG; // targets: walk positions, then negatives
 constexpr int SG_BLOCK = 256;             // four wavefronts
-// LDS row strides (bf16 elements), padded against bank conflicts
-constexpr int LD_V = SG_DIM + 8;    // V[c][d], T[t][d]
-constexpr int LD_VT = SG_MAXC + 8;  // Vt[d][c], Gt[t][c]
-constexpr int LD_TT = SG_T + 8;     // Tt[d][t], G[c][t]
+constexpr int LD_V = SG_DIM + 8;          // LDS row stride (bf16) of V[c][d] and T[t][d], padded against bank conflicts
 
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -54,21 +52,14 @@ struct SgArgs {
     float neg_weight;
 };
 
-// Row-major LDS tiles of one walk (139 KB; 16-byte aligned rows for the
-// operand loads).  After the logits, G and Gt take the place of V and T.
+// The rows of one walk in LDS, row-major bf16 (69 KB, so that two workgroups
+// share a CU): center rows V (win) and target rows T (wout: the walk's
+// positions, then its negatives).  The gradient products read the tables
+// across rows (see lds_rows8) instead of keeping transposed copies, and take
+// the coefficients straight from the logits' accumulators.
 struct alignas(16) SgLds {
-    union {
-        struct {
-            __bf16 V[SG_MAXC * LD_V];
-            __bf16 T[SG_T * LD_V];
-        } in;
-        struct {
-            __bf16 G[SG_MAXC * LD_TT];
-            __bf16 Gt[SG_T * LD_VT];
-        } g;
-    } u;
-    __bf16 Vt[SG_DIM * LD_VT];
-    __bf16 Tt[SG_DIM * LD_TT];
+    __bf16 V[SG_MAXC * LD_V];
+    __bf16 T[SG_T * LD_V];
     uint32_t ids[SG_T];
     float wloss[SG_BLOCK / WAVE];
 };
@@ -93,11 +84,54 @@ __device__ __forceinline__ f32x16 tile_dot(const __bf16 *A, int lda, int ra, con
 // Row of accumulator register r of lane l within a 32x32 tile (its column is l % 32).
 __device__ __forceinline__ int tile_row(int r) { return 8 * (r >> 2) + 4 * (lane_id() >> 5) + (r & 3); }
 
+// A tile's accumulator registers 8s .. 8s+7 of lane l hold rows 16s + 4 (l /
+// 32) + {0, 1, 2, 3, 8, 9, 10, 11} of column l % 32.  Used as the A operand
+// of a 16-deep k-step (lane l: row l % 32, k = 8 (l / 32) + j), they contract
+// over those rows in that order; this is the matching B operand from a
+// row-major LDS table M: lane l supplies M[r][d0 + l % 32] for the same eight
+// rows r, from r0 = tile base + 16s.
+__device__ __forceinline__ bf16x8 lds_rows8(const __bf16 *M, int r0, int d0)
+{
+    const int l = lane_id();
+    const __bf16 *p = M + (r0 + 4 * (l >> 5)) * LD_V + d0 + (l & 31);
+    bf16x8 b;
+    b[0] = p[0];
+    b[1] = p[LD_V];
+    b[2] = p[2 * LD_V];
+    b[3] = p[3 * LD_V];
+    b[4] = p[8 * LD_V];
+    b[5] = p[9 * LD_V];
+    b[6] = p[10 * LD_V];
+    b[7] = p[11 * LD_V];
+    return b;
+}
+
 __device__ __forceinline__ float softplus(float x) { return x > 0.f ? x + log1pf(expf(-x)) : log1pf(expf(x)); }
 
 __device__ __forceinline__ float sigmoid(float x) { return 1.f / (1.f + expf(-x)); }
 
-__global__ __launch_bounds__(SG_BLOCK, 1) void k_sg_walks(SgArgs A)
+// Gradient coefficient of the logit z of (center c, target t), adding its
+// loss term to `loss`: context pairs (a walk position within the window)
+// sigmoid(z) - 1, negatives neg_weight * sigmoid(z), anything else 0.
+__device__ __forceinline__ float sg_coef(const SgArgs &A, uint32_t len, uint32_t c, uint32_t t, float z, float &loss)
+{
+    if (c >= len) return 0.f;
+    if (t < (uint32_t)SG_MAXC) {
+        const uint32_t dist = c > t ? c - t : t - c;
+        if (t < len && dist >= 1 && dist <= A.window) {
+            loss += softplus(-z);
+            return sigmoid(z) - 1.f;
+        }
+        return 0.f;
+    }
+    if (t - SG_MAXC < A.nneg) {
+        loss += A.neg_weight * softplus(z);
+        return A.neg_weight * sigmoid(z);
+    }
+    return 0.f;
+}
+
+__global__ __launch_bounds__(SG_BLOCK, 2) void k_sg_walks(SgArgs A)
 {
     __shared__ SgLds S;
     const int tid = threadIdx.x, l = lane_id(), wv = tid / WAVE;
@@ -119,9 +153,8 @@ __global__ __launch_bounds__(SG_BLOCK, 1) void k_sg_walks(SgArgs A)
         const bool tv = tid < SG_MAXC ? (uint32_t)tid < len : (uint32_t)(tid - SG_MAXC) < A.nneg;
         if (tv) atomicAdd(A.cout + S.ids[tid], 1.f);
     }
-    // rows to bf16 tiles, row-major and transposed: 32 lanes per row, 4 floats
-    // each; a thread's GATHER rows are loaded together, so their latencies
-    // overlap instead of adding up
+    // rows to bf16 tiles: 32 lanes per row, 4 floats each; a thread's GATHER
+    // rows are loaded together, so their latencies overlap instead of adding up
     constexpr int NROWS = SG_MAXC + SG_T;                // 256 rows
     constexpr int RSTEP = SG_BLOCK / 32;                 // rows per pass of the block
     constexpr int GATHER = 32;                           // loads in flight per thread (one batch)
@@ -145,66 +178,65 @@ __global__ __launch_bounds__(SG_BLOCK, 1) void k_sg_walks(SgArgs A)
             const int r = r0 + k * RSTEP;
             const bool center = r < SG_MAXC;
             const int t = center ? r : r - SG_MAXC;
-            const __bf16 b0 = (__bf16)x[k].x, b1 = (__bf16)x[k].y, b2 = (__bf16)x[k].z, b3 = (__bf16)x[k].w;
-            __bf16 *dst = center ? S.u.in.V + t * LD_V : S.u.in.T + t * LD_V;
-            dst[4 * q] = b0;
-            dst[4 * q + 1] = b1;
-            dst[4 * q + 2] = b2;
-            dst[4 * q + 3] = b3;
-            __bf16 *tr = center ? S.Vt + t : S.Tt + t;
-            const int ld = center ? LD_VT : LD_TT;
-            tr[(4 * q) * ld] = b0;
-            tr[(4 * q + 1) * ld] = b1;
-            tr[(4 * q + 2) * ld] = b2;
-            tr[(4 * q + 3) * ld] = b3;
+            bf16x4 b;
+            b[0] = (__bf16)x[k].x;
+            b[1] = (__bf16)x[k].y;
+            b[2] = (__bf16)x[k].z;
+            b[3] = (__bf16)x[k].w;
+            *(bf16x4 *)((center ? S.V : S.T) + t * LD_V + 4 * q) = b;
         }
     }
     __syncthreads();
-    // logits: 3 x 5 tiles of 32 x 32, tile k of this wave is wv + 4k; gradient
-    // coefficients and the loss are formed in the accumulators
-    f32x16 gz[4];
+    // Eight units over the four wavefronts (unit wv and wv + 4), each for all
+    // four 32-wide column blocks of the 128 dimensions:
+    //   units 0..2: center gradients dV = G T of center block ci = u: the
+    //     logits of the block, transposed (Z^T = T V^T, lanes hold centers),
+    //     give the A operands directly, T rows the B operands;
+    //   units 3..7: target gradients dT = G^T V of target block tj = u - 3:
+    //     the logits Z = V T^T (lanes hold targets) give the A operands, V
+    //     rows the B operands; these units also add up the loss.
     float loss = 0.f;
+    for (int u = wv; u < 8; u += 4) {
+        const bool centers = u < 3;
+        const int blk = centers ? u : u - 3;
+        f32x16 acc[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int tile = wv + 4 * k;
-        if (tile < 15) {
-            const int ti = tile / 5, tj = tile % 5;
-            f32x16 z = tile_dot<SG_DIM>(S.u.in.V, LD_V, 32 * ti, S.u.in.T, LD_V, 32 * tj);
-            const uint32_t t = 32 * tj + (l & 31);
+        for (int dj = 0; dj < 4; ++dj) acc[dj] = f32x16{};
+        const int nk = centers ? SG_T / 32 : SG_MAXC / 32;  // 32-row blocks of the contraction
+        for (int kb = 0; kb < nk; ++kb) {
+            // logits tile: rows kb-block of the other side, columns (lanes) this unit's block
+            const f32x16 z = centers ? tile_dot<SG_DIM>(S.T, LD_V, 32 * kb, S.V, LD_V, 32 * blk)
+                                     : tile_dot<SG_DIM>(S.V, LD_V, 32 * kb, S.T, LD_V, 32 * blk);
+            bf16x8 a0, a1;
+            float dummy = 0.f;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const uint32_t c = 32 * ti + tile_row(r);
-                float g = 0.f;
-                if (c < len) {
-                    if (t < (uint32_t)SG_MAXC) {
-                        const uint32_t dist = c > t ? c - t : t - c;
-                        if (t < len && dist >= 1 && dist <= A.window) {
-                            g = sigmoid(z[r]) - 1.f;
-                            loss += softplus(-z[r]);
-                        }
-                    } else if (t - SG_MAXC < A.nneg) {
-                        g = A.neg_weight * sigmoid(z[r]);
-                        loss += A.neg_weight * softplus(z[r]);
-                    }
-                }
-                z[r] = g;
+                const uint32_t rr = 32 * kb + tile_row(r), ll = 32 * blk + (l & 31);
+                const float g = centers ? sg_coef(A, len, ll, rr, z[r], dummy) : sg_coef(A, len, rr, ll, z[r], loss);
+                if (r < 8) a0[r] = (__bf16)g;
+                else a1[r - 8] = (__bf16)g;
             }
-            gz[k] = z;
-        }
-    }
-    __syncthreads();  // V and T are read for the last time above
+            const __bf16 *M = centers ? S.T : S.V;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int tile = wv + 4 * k;
-        if (tile < 15) {
-            const int ti = tile / 5, tj = tile % 5;
-            const int t = 32 * tj + (l & 31);
+            for (int dj = 0; dj < 4; ++dj) {
+                acc[dj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, lds_rows8(M, 32 * kb, 32 * dj), acc[dj], 0, 0, 0);
+                acc[dj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, lds_rows8(M, 32 * kb + 16, 32 * dj), acc[dj], 0, 0,
+                                                                  0);
+            }
+        }
+        // rows of acc: this unit's block (centers or targets), columns d
+#pragma unroll
+        for (int dj = 0; dj < 4; ++dj) {
+            const int d = 32 * dj + (l & 31);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int c = 32 * ti + tile_row(r);
-                const __bf16 g = (__bf16)gz[k][r];
-                S.u.g.G[c * LD_TT + t] = g;
-                S.u.g.Gt[t * LD_VT + c] = g;
+                const uint32_t i = 32 * blk + tile_row(r);
+                if (centers) {
+                    if (i < len) atomicAdd(A.gin + (uint64_t)S.ids[i] * SG_DIM + d, acc[dj][r]);
+                } else {
+                    const bool valid = i < (uint32_t)SG_MAXC ? i < len : i - SG_MAXC < A.nneg;
+                    if (valid) atomicAdd(A.gout + (uint64_t)S.ids[i] * SG_DIM + d, acc[dj][r]);
+                }
             }
         }
     }
@@ -216,29 +248,6 @@ __global__ __launch_bounds__(SG_BLOCK, 1) void k_sg_walks(SgArgs A)
     if (tid == 0) {
         const float s = S.wloss[0] + S.wloss[1] + S.wloss[2] + S.wloss[3];
         if (s != 0.f) atomicAdd(A.loss, (double)s);
-    }
-    // center gradients dV = G T: 3 x 4 tiles, added into the input-side table
-    for (int tile = wv; tile < 12; tile += 4) {
-        const int ti = tile / 4, tj = tile % 4;
-        const f32x16 acc = tile_dot<SG_T>(S.u.g.G, LD_TT, 32 * ti, S.Tt, LD_TT, 32 * tj);
-        const int d = 32 * tj + (l & 31);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const uint32_t c = 32 * ti + tile_row(r);
-            if (c < len) atomicAdd(A.gin + (uint64_t)S.ids[c] * SG_DIM + d, acc[r]);
-        }
-    }
-    // target gradients dT = Gt V: 5 x 4 tiles, added into the output-side table
-    for (int tile = wv; tile < 20; tile += 4) {
-        const int ti = tile / 4, tj = tile % 4;
-        const f32x16 acc = tile_dot<SG_MAXC>(S.u.g.Gt, LD_VT, 32 * ti, S.Vt, LD_VT, 32 * tj);
-        const int d = 32 * tj + (l & 31);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const uint32_t t = 32 * ti + tile_row(r);
-            const bool valid = t < (uint32_t)SG_MAXC ? t < len : t - SG_MAXC < A.nneg;
-            if (valid) atomicAdd(A.gout + (uint64_t)S.ids[t] * SG_DIM + d, acc[r]);
-        }
     }
 }
 
