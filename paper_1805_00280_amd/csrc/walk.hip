@@ -238,23 +238,28 @@ __device__ __forceinline__ bool lds_contains(const uint32_t *T, uint32_t n, uint
     return n > 0 && *q == x;
 }
 
-// Thread class: attempts in order until one accepts (false after a_cap).
-__device__ bool thread_reject(const Exec &E, const JobCtx &J, const WS &st, uint32_t &j_out)
+// Thread class: attempts in order until one accepts (false after a_cap, or
+// after the first kmax attempts).
+__device__ bool thread_reject(const Exec &E, const JobCtx &J, const WS &st, uint32_t &j_out,
+                              uint32_t kmax = 0xFFFFFFFFu)
 {
-    for (uint32_t k = 0; k < E.g.a_cap; ++k)
+    const uint32_t n = kmax < E.g.a_cap ? kmax : E.g.a_cap;
+    for (uint32_t k = 0; k < n; ++k)
         if (attempt(E, J, st, k, j_out)) return true;
     return false;
 }
 
-// Wave class: lanes take attempts k0 + lane; the lowest accepting one wins.
+// Wave class: lanes take attempts k0 + lane (from attempt kfrom on, the
+// earlier ones having rejected); the lowest accepting one wins.
 // When some attempt needs "is x a neighbour of t?" and N(t) fits, the wave
 // stages N(t) in LDS once (one coalesced read) and searches it there.
-__device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, HubLds &L, uint32_t &j_out)
+__device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, HubLds &L, uint32_t &j_out,
+                            uint32_t kfrom = 0)
 {
     const WS st = uniform_ws(st_in);
     const int l = lane_id();
     bool staged = false;
-    for (uint32_t k0 = 0; k0 < E.g.a_cap; k0 += WAVE) {
+    for (uint32_t k0 = kfrom; k0 < E.g.a_cap; k0 += WAVE) {
         const uint32_t k = k0 + l;
         Att a;
         a.j = 0;
@@ -1621,19 +1626,25 @@ __device__ __forceinline__ void plain_finish(const Exec &E, const JobCtx &J, WS 
     if (!wave || lane_id() == 0) state[st.i] = make_uint4(end ? SENT : x, st.v, rev, j);
 }
 
+// Rejection attempts a lane of the plain thread kernel makes alone when a
+// superstep is small; its wavefront then takes the attempts that follow, 64
+// at a time, so that the superstep does not wait for one lane's long chain.
+// (A large superstep hides such chains behind other wavefronts.)
+constexpr uint32_t PLAIN_LANE_ATTEMPTS = 16;
+
 // Hub moves are queued for k_plain_hub: dense moves at degree > t_wg at the
 // top of hubq (growing down, one workgroup each), all others at the bottom.
-template <bool WALKS, bool COUNTS>
+template <bool WALKS, bool COUNTS, bool COOP>
 __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
                                                     uint32_t *__restrict__ hubq, uint32_t *__restrict__ hubn,
                                                     uint32_t *__restrict__ bign)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t csum = 0;
-    bool push = false, big = false;
+    bool push = false, big = false, pend = false;
     uint32_t item = 0;
+    WS st;
     if (i < S.n) {
-        WS st;
         if (plain_load(E, state[i], i, s, st)) {
             if (st.vd == 0) {
                 // the previous move reached a dead end: the rest of the row is N2V_SENT
@@ -1649,11 +1660,29 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
                 push = !big;
             } else {
                 uint32_t j;
-                if (thread_reject(E, S.c, st, j)) plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, false);
-                else {
-                    push = true;
+                if (thread_reject(E, S.c, st, j, COOP ? PLAIN_LANE_ATTEMPTS : 0xFFFFFFFFu)) {
+                    plain_finish<WALKS, COUNTS>(E, S.c, st, j, state, csum, false);
+                } else if (COOP) {
+                    pend = true;
+                } else {
+                    push = true;  // every attempt rejected: the inverse CDF of attempt a_cap
                     item = i | 0x80000000u;
                 }
+            }
+        }
+    }
+    if constexpr (COOP) {
+        __shared__ HubLds lds[256 / WAVE];
+        HubLds &L = lds[threadIdx.x / WAVE];
+        for (uint64_t pm = ballot(pend); pm; pm &= pm - 1) {
+            const int o = first_lane(pm);
+            WS w = bcast(st, o);
+            uint32_t j;
+            if (wave_reject(E, S.c, w, L, j, PLAIN_LANE_ATTEMPTS)) {
+                plain_finish<WALKS, COUNTS>(E, S.c, w, j, state, csum, true);
+            } else if (lane_id() == o) {
+                push = true;
+                item = i | 0x80000000u;
             }
         }
     }
@@ -1833,12 +1862,18 @@ int launch_plain(const Exec &E, const OneJob &S, void *ws, int dev, hipStream_t 
     DevInfo &d = dev_info(dev);
     const uint32_t hub_blocks = (uint32_t)d.cus * 8;
     // the thread kernel lasts as long as its slowest lane's chain of dependent
-    // reads: a small superstep is spread over every CU, one wavefront per block
+    // reads: a small superstep is spread over every CU, one wavefront per
+    // block, and its wavefronts finish their lanes' long rejection chains
+    // together
     const uint32_t tpb = S.n < (uint32_t)d.cus * 1024u ? 64u : 256u;
     const uint32_t sblocks = (S.n + tpb - 1) / tpb;
     for (uint32_t s = 0; s < S.c.L; ++s) {
-        hipLaunchKernelGGL((k_plain_step<W, C>), dim3(sblocks), dim3(tpb), 0, st, E, S, s, state, hubq, hubn + s,
-                           bign + s);
+        if (tpb == 64)
+            hipLaunchKernelGGL((k_plain_step<W, C, true>), dim3(sblocks), dim3(tpb), 0, st, E, S, s, state, hubq,
+                               hubn + s, bign + s);
+        else
+            hipLaunchKernelGGL((k_plain_step<W, C, false>), dim3(sblocks), dim3(tpb), 0, st, E, S, s, state, hubq,
+                               hubn + s, bign + s);
         hipLaunchKernelGGL((k_plain_hub<W, C>), dim3(hub_blocks), dim3(HBLOCK), 0, st, E, S, s, state, hubq,
                            (const uint32_t *)(hubn + s), hubd + s, (const uint32_t *)(bign + s), bigd + s);
     }

@@ -34,6 +34,11 @@ def test_measured_traffic_is_used_only_for_the_profiled_kernel(monkeypatch):
     assert t["bytes_per_launch"] == t["fetch_bytes"] + t["write_bytes"] > 0
     monkeypatch.setattr(bench, "kernel_sha", lambda: t["kernel_sha"])
     assert bench.load_traffic(name)["bytes_per_launch"] == t["bytes_per_launch"]
+    for sha in t.get("same_code_shas", []):
+        # sources whose persistent kernel compiles to the profiled instructions
+        monkeypatch.setattr(bench, "kernel_sha", lambda: sha)
+        assert bench.load_traffic(name)["bytes_per_launch"] == t["bytes_per_launch"]
+        assert "k_persistent" in t["same_code_check"]
     monkeypatch.setattr(bench, "kernel_sha", lambda: "0" * 16)
     assert bench.load_traffic(name) is None
     assert bench.load_traffic("no-such-workload") is None
