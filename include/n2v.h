@@ -253,8 +253,9 @@ int n2v_visit_profile(const n2v_graph *g, const uint32_t *cnt, uint32_t width, u
 /* Pair sketches (the FN-Cache paragraph of Section 3.4 keeps work done for
  * popular vertices for reuse): memory in which walk calls memoise, for every
  * traversed move (t -> v) at a vertex v of degree > d_rule, the exact number
- * of members of N(t) in each of 64 equal segments of N(v) and in each
- * segment's first half (as count + 1; 0 = unknown), and for each segment a
+ * of members of N(t) in each of nsup segments of N(v) (whole 512-entry tiles,
+ * at most 64 segments of equal tile counts) and in each segment's first half
+ * (as count + 1; 0 = unknown), and for each segment a
  * hint where its merge may start in N(t); on weighted graphs also, per
  * segment and per first half, the weight sum of those members (+ 1) and of
  * all entries (u32 words after the u16 ones).  A later move
@@ -269,8 +270,11 @@ int n2v_visit_profile(const n2v_graph *g, const uint32_t *cnt, uint32_t width, u
  * and fills the same memory, and overlapping calls only ever write equal
  * values into an entry.  Attaching clears the memory; n2v_graph_memo_clear
  * makes later calls start from unknown entries again (a cold pass).
- * n2v_graph_memo_bytes returns the size (hub entries x 384 bytes, or x 1408
- * for weighted graphs); n2v_graph_set_memo attaches caller device memory
+ * Each row is sized for its vertex: with nsp = nsup rounded up to even, a row
+ * of a vertex of degree d is 6 nsp bytes (22 nsp on weighted graphs), so a
+ * hub of degree d keeps d such rows (at most 384, or 1408, bytes each).
+ * n2v_graph_memo_bytes returns the size over every row of degree > d_rule;
+ * n2v_graph_set_memo attaches caller device memory
  * (NULL detaches).  Attaching synchronises the device, and returns N2V_EINVAL,
  * changing nothing, while a server created on the graph is alive. */
 int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes);

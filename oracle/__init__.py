@@ -69,6 +69,8 @@ def _load():
     lib.or_memo_cold_lines.restype = u64
     lib.or_memo_warm_lines.argtypes = [vp, i32, u32, u32]
     lib.or_memo_warm_lines.restype = u64
+    lib.or_memo_row_bytes.argtypes = [u64, i32]
+    lib.or_memo_row_bytes.restype = u64
     lib.or_memo_pass_bytes.argtypes = [vp, i32, vp, u64, u32, u32, u32, i32, vp]
     lib.or_memo_pass_bytes.restype = i32
     lib.or_approx_bounds.argtypes = [u64, u64, vp, u32, u32, vp, vp, vp, vp]
@@ -308,6 +310,11 @@ def memo_cold_lines(off, t, v, weighted=False):
 def memo_warm_lines(off, t, v, weighted=False):
     off = np.ascontiguousarray(off, dtype=np.uint64)
     return int(_load().or_memo_warm_lines(_ptr(off), int(weighted), t, v))
+
+
+def memo_row_bytes(d, weighted=False):
+    """Bytes of one pair-summary row of a vertex of degree d (or_memo_row_bytes)."""
+    return int(_load().or_memo_row_bytes(int(d), int(weighted)))
 
 
 def memo_pass_bytes(off, out, L, d_rule=D_RULE, memo_min=None, memo=True, weighted=False):

@@ -965,9 +965,22 @@ uint64_t or_memo_cold_lines(const uint64_t *off, int weighted, uint32_t t, uint3
     return search < dense ? search : dense;
 }
 
-/* Lines of one move at v after t that reads a summary.  A weighted graph's */
-/* summary row also holds four 32-bit weight sums per segment (22 lines),   */
-/* and the half segment's weights are read with its entries.               */
+/* Bytes of one summary row of a vertex of degree d: per segment a count,   */
+/* a start hint and a first-half count (16 bits each) and, on a weighted    */
+/* graph, four 32-bit weight sums, over the row's segments (whole 512-entry */
+/* tiles, at most 64 segments) rounded up to an even number.                */
+uint64_t or_memo_row_bytes(uint64_t d, int weighted)
+{
+    uint64_t tiles = (d + 511) / 512;
+    uint64_t per = tiles ? (tiles + 63) / 64 : 1;
+    uint64_t segs = (tiles + per - 1) / per;
+    segs = (segs + 1) & ~1ull;
+    return (weighted ? 22 : 6) * segs;
+}
+
+/* Lines of one move at v after t that reads a summary: the summary row,    */
+/* the half segment holding the draw (and its weights on a weighted graph) */
+/* and N(t)'s proportional share of it.                                     */
 uint64_t or_memo_warm_lines(const uint64_t *off, int weighted, uint32_t t, uint32_t v)
 {
     uint64_t dv = off[v + 1] - off[v], dt = off[t + 1] - off[t];
@@ -975,8 +988,9 @@ uint64_t or_memo_warm_lines(const uint64_t *off, int weighted, uint32_t t, uint3
     uint64_t seglen = ((tiles + 63) / 64) * 512;
     uint64_t h = seglen / 2 < dv ? seglen / 2 : dv;
     uint64_t ht = (dt * h + dv - 1) / dv;
-    if (weighted) return 22 + (4 * h + 63) / 64 + (2 * h + 63) / 64 + (4 * ht + 63) / 64;
-    return 6 + (4 * h + 63) / 64 + (4 * ht + 63) / 64;
+    uint64_t row = (or_memo_row_bytes(dv, weighted) + 63) / 64;
+    if (weighted) return row + (4 * h + 63) / 64 + (2 * h + 63) / 64 + (4 * ht + 63) / 64;
+    return row + (4 * h + 63) / 64 + (4 * ht + 63) / 64;
 }
 
 static int or_memo_keeps(uint64_t d, uint32_t memo_min)

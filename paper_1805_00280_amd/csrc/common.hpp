@@ -14,18 +14,28 @@ namespace n2v {
 
 constexpr uint32_t SENT = 0xFFFFFFFFu;
 constexpr int WAVE = 64;
-// Segments per pair sketch: a sketch of the move (t -> v) at a hub v holds,
-// for each of up to MEMO_SEGS segments of N(v), one plus the number of
-// members of N(t) in that segment (0 = not known yet), then, per segment, a
-// start hint into N(t), then one plus the count in the segment's first half
-// (MEMO_ROW u16 per sketch).
+// Pair sketches.  A sketch of the move (t -> v) at a hub v splits N(v) into
+// at most MEMO_SEGS segments of whole 512-entry tiles (nsup of them) and
+// holds, per segment, one plus the number of members of N(t) in the segment
+// (0 = not known yet), then per segment a start hint into N(t), then one plus
+// the count in the segment's first half: three u16 arrays of nsp entries
+// each, nsp = nsup rounded up to even (memo_segs).  Rows of weighted graphs
+// append, as u32, per segment the weight sum of its members of N(t), the same
+// over its first half, the weight sum of all its entries and the same over
+// its first half.  Each row is sized for its own vertex: memo_row_words u16
+// words for a vertex of degree d, a whole number of 4-byte words.
 constexpr int MEMO_SEGS = 64;
-constexpr int MEMO_ROW = 3 * MEMO_SEGS;
-// Rows of weighted graphs append, as u32 after the 3 x MEMO_SEGS u16 words,
-// per segment the weight sum of its members of N(t), the same over its first
-// half, the weight sum of all its entries and the same over its first half.
-constexpr int MEMO_ROW_W = 3 * MEMO_SEGS + 8 * MEMO_SEGS;
-__host__ __device__ constexpr int memo_row_words(bool weighted) { return weighted ? MEMO_ROW_W : MEMO_ROW; }
+__host__ __device__ inline uint32_t memo_segs(uint64_t d)
+{
+    const uint64_t tiles = (d + 511) / 512;
+    const uint64_t per = tiles > 0 ? (tiles + MEMO_SEGS - 1) / MEMO_SEGS : 1;  // tiles per segment
+    const uint32_t nsup = (uint32_t)((tiles + per - 1) / per);
+    return (nsup + 1) & ~1u;
+}
+__host__ __device__ inline uint32_t memo_row_words(bool weighted, uint64_t d)
+{
+    return (weighted ? 11u : 3u) * memo_segs(d);
+}
 // Sketches serve rows of at most this degree: 127 tiles of 512 entries per
 // segment, so count + 1 always fits the u16 entries (and a segment's weight
 // sum, at most 65024 x 65535, a u32).
@@ -64,8 +74,8 @@ struct DevGraph {
     const uint32_t *adj;   // m, rows strictly ascending
     const uint16_t *wt;    // m, or null for an unweighted graph
     const uint64_t *wsum;  // n: row weight sums (weighted graphs only)
-    const uint64_t *hbase; // n+1: first sketch row of each vertex of degree >= memo_min
-    uint16_t *memo;        // pair sketches (hbase[n] rows of MEMO_ROW u16) or null
+    const uint64_t *hbase; // n+1: u16 word offset of the sketch rows of each vertex of degree >= memo_min
+    uint16_t *memo;        // pair sketches (hbase[n] u16 words; deg(v) rows of memo_row_words each) or null
     uint32_t *status;      // device flags: bit 0 = a start id was out of range
     uint32_t *cursors;     // CURSOR_SLOTS walk counters, one per concurrent call
     uint32_t n;
@@ -238,8 +248,8 @@ struct n2v_graph {
     int device;
     bool has_tuned;
     n2v_exec_opts tuned;
-    uint64_t hub_entries;   // entries in rows of degree > d_rule
-    uint64_t memo_entries;  // entries in rows of degree >= dg.memo_min (sketch rows)
+    uint64_t hub_words;     // sketch words of the rows of degree > d_rule
+    uint64_t memo_words;    // sketch words of the rows of degree >= dg.memo_min
     void *scan;             // scan scratch of the graph's workspace
     unsigned long long *hist;  // 64 words of the graph's workspace for degree statistics
     uint32_t next_cursor;   // next walk-counter slot to try

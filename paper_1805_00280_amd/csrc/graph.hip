@@ -94,20 +94,24 @@ __global__ __launch_bounds__(256) void k_derive(const uint64_t *__restrict__ off
     if (flags) atomicOr(bad, flags);
 }
 
-// hbase[v] = deg(v) when deg(v) >= dmin, else 0 (scanned afterwards).
-__global__ void k_hub_len(const uint64_t *__restrict__ off, uint32_t n, uint64_t dmin, uint64_t *__restrict__ hb)
+// Sketch words of a vertex of degree d: d rows of memo_row_words(d).
+__device__ __forceinline__ uint64_t sketch_words(uint64_t d, bool weighted) { return d * memo_row_words(weighted, d); }
+
+// hbase[v] = sketch words of v when deg(v) >= dmin, else 0 (scanned afterwards).
+__global__ void k_hub_len(const uint64_t *__restrict__ off, uint32_t n, uint64_t dmin, bool weighted,
+                          uint64_t *__restrict__ hb)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride) {
         const uint64_t d = v < n ? off[v + 1] - off[v] : 0;
-        hb[v] = d >= dmin ? d : 0;
+        hb[v] = d >= dmin && d > 0 ? sketch_words(d, weighted) : 0;
     }
 }
 
-// Entries in rows of degree in [2^k, 2^(k+1)), k = 0..63, over rows of degree
-// >= dmin (a per-block histogram, then one atomic per bin).
+// Sketch words of the rows of degree in [2^k, 2^(k+1)), k = 0..63, over rows
+// of degree >= dmin (a per-block histogram, then one atomic per bin).
 __global__ __launch_bounds__(256) void k_deg_hist(const uint64_t *__restrict__ off, uint32_t n, uint64_t dmin,
-                                                  unsigned long long *__restrict__ hist)
+                                                  bool weighted, unsigned long long *__restrict__ hist)
 {
     __shared__ unsigned long long h[64];
     if (threadIdx.x < 64) h[threadIdx.x] = 0;
@@ -115,21 +119,22 @@ __global__ __launch_bounds__(256) void k_deg_hist(const uint64_t *__restrict__ o
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
         const uint64_t d = off[v + 1] - off[v];
-        if (d >= dmin && d > 0) atomicAdd(&h[63 - __clzll((long long)d)], (unsigned long long)d);
+        if (d >= dmin && d > 0) atomicAdd(&h[63 - __clzll((long long)d)], (unsigned long long)sketch_words(d, weighted));
     }
     __syncthreads();
     if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-// Sum of the degrees >= dmin (per-block reduction, one atomic per block).
+// Sketch words of the rows of degree >= dmin (per-block reduction, one
+// atomic per block).
 __global__ __launch_bounds__(256) void k_deg_sum_ge(const uint64_t *__restrict__ off, uint32_t n, uint64_t dmin,
-                                                    unsigned long long *__restrict__ out)
+                                                    bool weighted, unsigned long long *__restrict__ out)
 {
     unsigned long long acc = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
         const uint64_t d = off[v + 1] - off[v];
-        if (d >= dmin) acc += d;
+        if (d >= dmin && d > 0) acc += sketch_words(d, weighted);
     }
     acc = wave_sum(acc);
     __shared__ unsigned long long part[256 / WAVE];
@@ -245,13 +250,14 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
         if (bad) return set_error(N2V_EGRAPH, "n2v_graph_create: CSR is not symmetric (flags 0x%x)", bad);
     }
     const uint64_t memo_min = (uint64_t)o.d_rule + 1;
-    hipLaunchKernelGGL(k_hub_len, dim3(grid_for_waves(n)), dim3(256), 0, st, off, n, memo_min, L.hbase);
+    hipLaunchKernelGGL(k_hub_len, dim3(grid_for_waves(n)), dim3(256), 0, st, off, n, memo_min, wt != nullptr,
+                       L.hbase);
     N2V_HIP(hipGetLastError());
     int rc = exclusive_scan_u64(L.hbase, (uint64_t)n + 1, L.scan, st);
     if (rc) return rc;
-    uint64_t hub_entries = 0;
+    uint64_t hub_words = 0;
     uint32_t wrange[2] = {0, 0};
-    N2V_HIP(hipMemcpyAsync(&hub_entries, L.hbase + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    N2V_HIP(hipMemcpyAsync(&hub_words, L.hbase + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     N2V_HIP(hipMemcpyAsync(wrange, L.status + 2, sizeof(wrange), hipMemcpyDeviceToHost, st));
     N2V_HIP(hipStreamSynchronize(st));
     n2v_graph *g = (n2v_graph *)calloc(1, sizeof(n2v_graph));
@@ -265,8 +271,8 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
     g->servers = 0;
     g->dg.hbase = L.hbase;
     g->dg.memo = nullptr;
-    g->hub_entries = hub_entries;
-    g->memo_entries = hub_entries;
+    g->hub_words = hub_words;
+    g->memo_words = hub_words;
     g->scan = L.scan;
     g->memo_bytes = 0;
     g->dg.vrec = L.vrec;
@@ -322,7 +328,7 @@ extern "C" int n2v_graph_info(const n2v_graph *g, uint32_t *n, uint64_t *m, uint
 extern "C" int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes)
 {
     if (!g || !bytes) return set_error(N2V_EINVAL, "n2v_graph_memo_bytes: null argument");
-    *bytes = (size_t)g->hub_entries * memo_row_words(g->weighted) * sizeof(uint16_t);
+    *bytes = (size_t)g->hub_words * sizeof(uint16_t);
     return N2V_OK;
 }
 
@@ -333,14 +339,15 @@ __global__ void k_zero_u64w(unsigned long long *p, uint32_t n)
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-// Entries in rows of degree >= dmin, through the graph's statistics words
-// (synchronous on the default stream).
+// Sketch words of the rows of degree >= dmin, through the graph's statistics
+// words (synchronous on the default stream).
 unsigned long long deg_sum_ge(const n2v_graph *g, uint64_t dmin, int *rc)
 {
     unsigned long long e = 0;
     *rc = N2V_OK;
     hipLaunchKernelGGL(k_zero_u64w, dim3(1), dim3(64), 0, 0, g->hist, 1u);
-    hipLaunchKernelGGL(k_deg_sum_ge, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin, g->hist);
+    hipLaunchKernelGGL(k_deg_sum_ge, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin,
+                       g->weighted != 0, g->hist);
     hipError_t err = hipGetLastError();
     if (err == hipSuccess) err = hipMemcpy(&e, g->hist, sizeof(e), hipMemcpyDeviceToHost);
     if (err != hipSuccess) *rc = hip_fail(err, "degree sum");
@@ -352,18 +359,19 @@ unsigned long long deg_sum_ge(const n2v_graph *g, uint64_t dmin, int *rc)
 extern "C" int n2v_graph_memo_plan(const n2v_graph *g, size_t budget, uint32_t *min_degree, size_t *bytes)
 {
     if (!g || !min_degree || !bytes) return set_error(N2V_EINVAL, "n2v_graph_memo_plan: null argument");
-    const size_t row = memo_row_words(g->weighted) * sizeof(uint16_t);
+    const size_t row = sizeof(uint16_t);  // bytes per sketch word
     const uint64_t dmin = (uint64_t)g->dg.d_rule + 1;
-    if (g->hub_entries * row <= budget) {
+    if (g->hub_words * row <= budget) {
         *min_degree = (uint32_t)std::min<uint64_t>(dmin, 0xFFFFFFFFull);
-        *bytes = g->hub_entries * row;
+        *bytes = g->hub_words * row;
         return N2V_OK;
     }
     // degree statistics go through 64 words of the graph's own workspace
     unsigned long long *hist = g->hist;
     unsigned long long h[64];
     hipLaunchKernelGGL(k_zero_u64w, dim3(1), dim3(64), 0, 0, hist, 64u);
-    hipLaunchKernelGGL(k_deg_hist, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin, hist);
+    hipLaunchKernelGGL(k_deg_hist, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin,
+                       g->weighted != 0, hist);
     N2V_HIP(hipGetLastError());
     N2V_HIP(hipMemcpy(h, hist, sizeof(h), hipMemcpyDeviceToHost));
     int rc = N2V_OK;
@@ -439,13 +447,13 @@ extern "C" int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uin
     const uint64_t dmin = std::max<uint64_t>(min_degree, (uint64_t)g->dg.d_rule + 1);
     // the rows the threshold keeps are counted before anything changes, so a
     // refusal leaves the handle exactly as it was
-    uint64_t rows = g->memo_entries;
+    uint64_t words = g->memo_words;
     if (dmin != g->dg.memo_min) {
         int rc = N2V_OK;
-        rows = deg_sum_ge(g, dmin, &rc);
+        words = deg_sum_ge(g, dmin, &rc);
         if (rc) return rc;
     }
-    const size_t need = (size_t)rows * memo_row_words(g->weighted) * sizeof(uint16_t);
+    const size_t need = (size_t)words * sizeof(uint16_t);
     if (bytes < need) return set_error(N2V_ENOMEM, "n2v_graph_set_memo: %zu < %zu bytes", bytes, need);
     // detached while the rows are re-indexed: a failure below leaves no
     // memory attached rather than memory indexed for another threshold
@@ -453,11 +461,11 @@ extern "C" int n2v_graph_set_memo_min(n2v_graph *g, void *mem, size_t bytes, uin
     g->memo_bytes = 0;
     if (dmin != g->dg.memo_min) {
         hipLaunchKernelGGL(k_hub_len, dim3(grid_for_waves(g->dg.n)), dim3(256), 0, 0, g->off, g->dg.n, dmin,
-                           (uint64_t *)g->dg.hbase);
+                           g->weighted != 0, (uint64_t *)g->dg.hbase);
         N2V_HIP(hipGetLastError());
         int rc = exclusive_scan_u64((uint64_t *)g->dg.hbase, (uint64_t)g->dg.n + 1, g->scan, 0);
         if (rc) return rc;
-        g->memo_entries = rows;
+        g->memo_words = words;
         g->dg.memo_min = (uint32_t)std::min<uint64_t>(dmin, 0xFFFFFFFFull);
     }
     // every entry starts unknown

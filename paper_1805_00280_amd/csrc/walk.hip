@@ -289,8 +289,9 @@ __device__ bool wave_reject(const Exec &E, const JobCtx &J, const WS &st_in, Hub
 }
 
 // ------------------------------------------------------------------ hubs
-// Sketch rows: MEMO_SEGS counts (one plus the number of members of N(t) in
-// a segment of N(v); 0 = unknown), then MEMO_SEGS start hints: hint h > 0 of a
+// Sketch rows (nsp = memo_segs(deg v) entries per array): counts (one plus
+// the number of members of N(t) in a segment of N(v); 0 = unknown), then
+// start hints: hint h > 0 of a
 // segment says that its merge may start streaming N(t) at index
 // (h - 1) << hint_shift(deg t), which is at or below the lower bound in N(t)
 // of the segment's first entry (so the skipped entries cannot match).
@@ -305,6 +306,7 @@ __device__ __forceinline__ uint32_t hint_shift(uint32_t d)
 // for each segment's first entry, its lower bound in N(v) as a start hint.
 struct RevSketch {
     uint32_t rseg;   // segment length of N(t); 0: not collected
+    uint32_t nsp;    // entries per array of t's sketch row (memo_segs(deg t))
     uint32_t shift;  // hint_shift(deg v)
     uint32_t *rc;    // LDS counts
     uint32_t *rh;    // LDS encoded hints
@@ -582,9 +584,9 @@ __device__ __forceinline__ uint64_t seg_pi(const JobCtx &J, uint32_t pos_t, uint
 }
 
 // Sketch row of the move at v from t (t at index pos_t of N(v)), or null.
-__device__ __forceinline__ uint16_t *sketch_row(const Exec &E, uint32_t v, uint32_t pos_t)
+__device__ __forceinline__ uint16_t *sketch_row(const Exec &E, uint32_t v, uint32_t d, uint32_t pos_t)
 {
-    return E.g.memo + (E.g.hbase[v] + pos_t) * (uint64_t)memo_row_words(E.g.wt != nullptr);
+    return E.g.memo + E.g.hbase[v] + pos_t * (uint64_t)memo_row_words(E.g.wt != nullptr, d);
 }
 
 // The same for the move at st.v, from the first sketch row loaded with v's
@@ -592,7 +594,7 @@ __device__ __forceinline__ uint16_t *sketch_row(const Exec &E, uint32_t v, uint3
 __device__ __forceinline__ uint16_t *sketch_row(const Exec &E, const WS &st, uint32_t pos_t)
 {
     const uint64_t hb = st.hb != ~0ull ? st.hb : E.g.hbase[st.v];
-    return E.g.memo + (hb + pos_t) * (uint64_t)memo_row_words(E.g.wt != nullptr);
+    return E.g.memo + hb + pos_t * (uint64_t)memo_row_words(E.g.wt != nullptr, st.vd);
 }
 
 // Weight sums of a tile whose flags are in LDS: all entries, flagged entries,
@@ -643,7 +645,8 @@ __device__ __forceinline__ uint16_t *rev_setup(const Exec &E, const WS &st, uint
     const uint32_t tsub = (st.td + TX - 1) / TX;
     const uint32_t tG = (tsub + NSUPER - 1) / NSUPER;
     R.rseg = tG * TX;
-    return sketch_row(E, st.t, st.jprev);
+    R.nsp = memo_segs(st.td);
+    return sketch_row(E, st.t, st.td, st.jprev);
 }
 
 // Dense inverse CDF of a second-order move over all of N(v): per-segment sums
@@ -666,7 +669,8 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     if (E.g.memo && pos_t != SENT && dv >= E.g.memo_min && dv <= MEMO_MAX_DEG) row = sketch_row(E, st, pos_t);
     // weighted rows: per-segment weight sums after the u16 words (members of
     // N(t) + 1, the same over the first half + 1, all entries, first half)
-    uint32_t *row32 = row && W ? (uint32_t *)(row + 3 * MEMO_SEGS) : nullptr;
+    const uint32_t nsp = memo_segs(dv);  // entries per array of the row
+    uint32_t *row32 = row && W ? (uint32_t *)(row + 3 * nsp) : nullptr;
     const uint64_t wt_t = W && pos_t != SENT ? W[pos_t] : 0u;
     bool warm = false;
     // per segment (lane): count + 1; where its stream of N(t) may start (SENT:
@@ -677,8 +681,8 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     if (row) {
         if ((uint32_t)l < nsup) {
             known = row[l];
-            halfv = row[2 * MEMO_SEGS + l];
-            const uint32_t h = row[MEMO_SEGS + l];
+            halfv = row[2 * nsp + l];
+            const uint32_t h = row[nsp + l];
             if (h) {
                 ystart = (h - 1) << hs;
                 const uint64_t up = (uint64_t)h << hs;
@@ -687,9 +691,9 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             if (row32) {
                 // a word is 0 until written, and every writer writes the same
                 // value: a segment is known when all of its words are
-                const uint32_t cw = row32[l], cw1 = row32[MEMO_SEGS + l];
-                segw = row32[2 * MEMO_SEGS + l];
-                segw1 = row32[3 * MEMO_SEGS + l];
+                const uint32_t cw = row32[l], cw1 = row32[nsp + l];
+                segw = row32[2 * nsp + l];
+                segw1 = row32[3 * nsp + l];
                 if (cw == 0 || segw == 0) known = 0;
                 if (cw1 == 0 || segw1 == 0) halfv = 0;
                 segcw = cw - 1;
@@ -774,21 +778,21 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
         }
         if (row && (uint32_t)l < nsup) {
             __builtin_nontemporal_store((uint16_t)(mine + 1), row + l);
-            __builtin_nontemporal_store((uint16_t)((ystart >> hs) + 1), row + MEMO_SEGS + l);
-            __builtin_nontemporal_store((uint16_t)halfv, row + 2 * MEMO_SEGS + l);
+            __builtin_nontemporal_store((uint16_t)((ystart >> hs) + 1), row + nsp + l);
+            __builtin_nontemporal_store((uint16_t)halfv, row + 2 * nsp + l);
             if (row32) {
                 __builtin_nontemporal_store(segcw + 1, row32 + l);
-                __builtin_nontemporal_store(segcw1 + 1, row32 + MEMO_SEGS + l);
-                __builtin_nontemporal_store(segw, row32 + 2 * MEMO_SEGS + l);
-                __builtin_nontemporal_store(segw1, row32 + 3 * MEMO_SEGS + l);
+                __builtin_nontemporal_store(segcw1 + 1, row32 + nsp + l);
+                __builtin_nontemporal_store(segw, row32 + 2 * nsp + l);
+                __builtin_nontemporal_store(segw1, row32 + 3 * nsp + l);
             }
         }
         ycap = ystart;
         const uint32_t rsup = R.rseg ? (td + R.rseg - 1) / R.rseg : 0;
         if (rrow && (uint32_t)l < rsup) {
             __builtin_nontemporal_store((uint16_t)(L.a.d.rc[l] + 1), rrow + l);
-            __builtin_nontemporal_store((uint16_t)L.a.d.rh[l], rrow + MEMO_SEGS + l);
-            __builtin_nontemporal_store((uint16_t)(L.a.d.r1[l] + 1), rrow + 2 * MEMO_SEGS + l);
+            __builtin_nontemporal_store((uint16_t)L.a.d.rh[l], rrow + R.nsp + l);
+            __builtin_nontemporal_store((uint16_t)(L.a.d.r1[l] + 1), rrow + 2 * R.nsp + l);
         }
     }
     wave_lds_sync();
@@ -853,7 +857,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     const bool srch = (uint64_t)(yend - ypos) > (uint64_t)E.search_ratio * (xb - xa);
     const uint32_t np = pivots_for(xb - xa);
     const uint32_t B = srch ? load_pivots(Y, ypos, yend, L, np) : 0;
-    const RevSketch none = {0, 0, nullptr, nullptr, nullptr};
+    const RevSketch none = {};
     for (uint32_t j0 = xa; j0 < xb; j0 += TX) {
         const uint32_t cnt = xb - j0 < (uint32_t)TX ? xb - j0 : (uint32_t)TX;
         if (srch) {
@@ -1006,7 +1010,7 @@ __device__ uint32_t hub_sparse(const Exec &E, const JobCtx &J, const WS &st, Hub
         if ((uint32_t)l < nsup) {
             uint16_t *row = sketch_row(E, st, st.pos_t);
             __builtin_nontemporal_store((uint16_t)(cnt[l] + 1), row + l);
-            __builtin_nontemporal_store((uint16_t)(cnt1[l] + 1), row + 2 * MEMO_SEGS + l);
+            __builtin_nontemporal_store((uint16_t)(cnt1[l] + 1), row + 2 * memo_segs(dv) + l);
         }
         wave_lds_sync();
     }
@@ -1105,7 +1109,7 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
         if (row) {
             if ((uint32_t)l < nsup) {
                 known = row[l];
-                const uint32_t h = row[MEMO_SEGS + l];
+                const uint32_t h = row[memo_segs(dv) + l];
                 if (h) {
                     ys = (h - 1) << hs;
                     const uint64_t up = (uint64_t)h << hs;
@@ -1162,7 +1166,7 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
                     B.ycap[sp] = ys;
                     if (row) {
                         __builtin_nontemporal_store((uint16_t)(csp + 1), row + sp);
-                        __builtin_nontemporal_store((uint16_t)((ys >> hs) + 1), row + MEMO_SEGS + sp);
+                        __builtin_nontemporal_store((uint16_t)((ys >> hs) + 1), row + memo_segs(dv) + sp);
                     }
                 }
             }
@@ -1171,8 +1175,8 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
         const uint32_t rsup = R.rseg ? (td + R.rseg - 1) / R.rseg : 0;
         if (wv == 0 && rrow && (uint32_t)l < rsup) {
             __builtin_nontemporal_store((uint16_t)(B.rc[l] + 1), rrow + l);
-            __builtin_nontemporal_store((uint16_t)B.rh[l], rrow + MEMO_SEGS + l);
-            __builtin_nontemporal_store((uint16_t)(B.r1[l] + 1), rrow + 2 * MEMO_SEGS + l);
+            __builtin_nontemporal_store((uint16_t)B.rh[l], rrow + R.nsp + l);
+            __builtin_nontemporal_store((uint16_t)(B.r1[l] + 1), rrow + 2 * R.nsp + l);
         }
     }
     // every wavefront finds the same segment from the shared sums
@@ -1191,7 +1195,7 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
     if (yhi < ylo) yhi = ylo;
     const uint32_t xlen = dv - spx * seglen < seglen ? dv - spx * seglen : seglen;
     const bool lsrch = (uint64_t)(yhi - ylo) > (uint64_t)E.search_ratio * xlen;
-    const RevSketch none = {0, 0, nullptr, nullptr};
+    const RevSketch none = {};
     const uint32_t sub_end = nsub < (spx + 1) * G ? nsub : (spx + 1) * G;
     const uint32_t Bl = lsrch && spx * G + wv < sub_end ? load_pivots(Y, ylo, yhi, L, NPIV) : 0;
     for (uint32_t b = spx * G; b < sub_end; b += HWAVES) {
@@ -1415,9 +1419,24 @@ __device__ __forceinline__ void ws_to_slot(const WS &st, uint32_t flags, Slot &q
     q.flags = flags;
 }
 
-template <class Src, bool WALKS, bool COUNTS>
-__global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E, Src S)
+// The graph view a kernel instantiated for unweighted graphs (WT false)
+// works with: a null weight array the compiler can see, so the weighted
+// branches of every move drop out of its code (and its registers).
+template <bool WT>
+__device__ __forceinline__ Exec exec_for(const Exec &E)
 {
+    Exec e = E;
+    if (!WT) {
+        e.g.wt = nullptr;
+        e.g.wsum = nullptr;
+    }
+    return e;
+}
+
+template <class Src, bool WALKS, bool COUNTS, bool WT>
+__global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E_arg, Src S)
+{
+    const Exec E = exec_for<WT>(E_arg);
     __shared__ HubLds lds[PBLOCK / WAVE];
     __shared__ Slot slots[PBLOCK / WAVE][WAVE];
     HubLds &L = lds[threadIdx.x / WAVE];
@@ -1711,12 +1730,13 @@ __global__ __launch_bounds__(256) void k_plain_step(Exec E, OneJob S, uint32_t s
 // The hub moves of this superstep: first the large dense ones, one workgroup
 // each (largest work first shortens the superstep's tail), then the rest,
 // one wavefront each.
-template <bool WALKS, bool COUNTS>
-__global__ __launch_bounds__(HBLOCK, 5) void k_plain_hub(Exec E, OneJob S, uint32_t s, uint4 *__restrict__ state,
+template <bool WALKS, bool COUNTS, bool WT>
+__global__ __launch_bounds__(HBLOCK, 5) void k_plain_hub(Exec E_arg, OneJob S, uint32_t s, uint4 *__restrict__ state,
                                                          const uint32_t *__restrict__ hubq,
                                                          const uint32_t *__restrict__ hubn, uint32_t *__restrict__ hubd,
                                                          const uint32_t *__restrict__ bign, uint32_t *__restrict__ bigd)
 {
+    const Exec E = exec_for<WT>(E_arg);
     __shared__ HubLds lds[HBLOCK / WAVE];
     __shared__ BlkLds blk;
     HubLds &L = lds[threadIdx.x / WAVE];
@@ -1806,7 +1826,7 @@ DevInfo &dev_info(int dev)
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) d.cus = prop.multiProcessorCount;
         if (d.cus <= 0) d.cus = 256;
         int b = 0;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)k_persistent<OneJob, true, true>,
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)k_persistent<OneJob, true, true, true>,
                                                            PBLOCK, 0);
         d.occ = b > 0 ? b : 2;
     }
@@ -1839,7 +1859,12 @@ template <bool W, bool C>
 int launch_persistent(const Exec &E, const OneJob &S, const n2v_exec_opts &o, int dev, hipStream_t st)
 {
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, S.cur, 1u);
-    hipLaunchKernelGGL((k_persistent<OneJob, W, C>), dim3(persistent_blocks(o, dev, S.n)), dim3(PBLOCK), 0, st, E, S);
+    if (E.g.wt)
+        hipLaunchKernelGGL((k_persistent<OneJob, W, C, true>), dim3(persistent_blocks(o, dev, S.n)), dim3(PBLOCK), 0,
+                           st, E, S);
+    else
+        hipLaunchKernelGGL((k_persistent<OneJob, W, C, false>), dim3(persistent_blocks(o, dev, S.n)), dim3(PBLOCK), 0,
+                           st, E, S);
     N2V_HIP(hipGetLastError());
     return N2V_OK;
 }
@@ -1874,8 +1899,12 @@ int launch_plain(const Exec &E, const OneJob &S, void *ws, int dev, hipStream_t 
         else
             hipLaunchKernelGGL((k_plain_step<W, C, false>), dim3(sblocks), dim3(tpb), 0, st, E, S, s, state, hubq,
                                hubn + s, bign + s);
-        hipLaunchKernelGGL((k_plain_hub<W, C>), dim3(hub_blocks), dim3(HBLOCK), 0, st, E, S, s, state, hubq,
-                           (const uint32_t *)(hubn + s), hubd + s, (const uint32_t *)(bign + s), bigd + s);
+        if (E.g.wt)
+            hipLaunchKernelGGL((k_plain_hub<W, C, true>), dim3(hub_blocks), dim3(HBLOCK), 0, st, E, S, s, state, hubq,
+                               (const uint32_t *)(hubn + s), hubd + s, (const uint32_t *)(bign + s), bigd + s);
+        else
+            hipLaunchKernelGGL((k_plain_hub<W, C, false>), dim3(hub_blocks), dim3(HBLOCK), 0, st, E, S, s, state,
+                               hubq, (const uint32_t *)(hubn + s), hubd + s, (const uint32_t *)(bign + s), bigd + s);
     }
     N2V_HIP(hipGetLastError());
     return N2V_OK;
@@ -2121,7 +2150,10 @@ int launch_job_table(const Exec &E, const TableHdr *hdr, uint32_t blocks, hipStr
 {
     JobTable T;
     T.hdr = hdr;
-    hipLaunchKernelGGL((k_persistent<JobTable, true, false>), dim3(blocks), dim3(PBLOCK), 0, st, E, T);
+    if (E.g.wt)
+        hipLaunchKernelGGL((k_persistent<JobTable, true, false, true>), dim3(blocks), dim3(PBLOCK), 0, st, E, T);
+    else
+        hipLaunchKernelGGL((k_persistent<JobTable, true, false, false>), dim3(blocks), dim3(PBLOCK), 0, st, E, T);
     N2V_HIP(hipGetLastError());
     return N2V_OK;
 }

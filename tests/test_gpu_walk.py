@@ -154,7 +154,7 @@ def test_workgroup_hub_class(weighted, memo):
         assert first_mismatch(got, want) is None, (t_wg, search, first_mismatch(got, want))
     if memo:
         torch.cuda.synchronize()
-        n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 704 if weighted else 192), 101)
+        n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16), 101)
         assert n > 100
         g.detach_memo()
 
@@ -300,28 +300,49 @@ def hint_shift(d):
     return max(0, int(d).bit_length() - 15)
 
 
+def memo_segs(d):
+    """Entries per array of a sketch row of a vertex of degree d: its segment count, rounded up to
+    even (every row a whole number of 4-byte words)."""
+    _, nsup = sketch_segments(int(d))
+    return (nsup + 1) & ~1
+
+
+def row_words(d, weighted):
+    return (11 if weighted else 3) * memo_segs(d)
+
+
+def sketch_bytes(deg, min_deg, weighted=False):
+    """Sketch memory of the rows of degree >= min_deg: deg(v) rows of row_words(deg v) u16 each."""
+    return sum(2 * int(d) * row_words(d, weighted) for d in deg[deg >= min_deg] if d > 0)
+
+
 def check_sketch_rows(og, memo, min_deg, limit=6000, seed=1):
     """Every written pair-sketch row (v, index of t in N(v)) holds, per segment of N(v), one plus the
     number of its entries that are neighbours of t; start hints into N(t) at or below the lower
     bound of the segment's first entry and not below the end of the previous segment's matches; and
     one plus the number in the segment's first half (0 where unknown). Unwritten rows and entries
-    are zero."""
+    are zero.  `memo` is the flat u16 sketch memory: the rows of each vertex of degree >= min_deg in
+    vertex order, deg(v) rows of row_words(deg v) words each."""
     deg = og.degree()
-    hub = deg >= min_deg
-    hb = np.zeros(og.n + 1, dtype=np.int64)
-    hb[1:] = np.cumsum(np.where(hub, deg, 0))
-    rows = memo
     weighted = og.wt is not None
-    assert rows.shape[0] >= hb[-1] and rows.shape[1] == (704 if weighted else 192)
-    sums = np.ascontiguousarray(rows[:, 192:]).view(np.uint32) if weighted else None
-    touched = np.nonzero(rows[:hb[-1]].any(axis=1))[0]
+    hub = (deg >= min_deg) & (deg > 0)
+    words = np.array([int(d) * row_words(d, weighted) if h else 0 for d, h in zip(deg, hub)], dtype=np.int64)
+    hb = np.zeros(og.n + 1, dtype=np.int64)
+    hb[1:] = np.cumsum(words)
+    assert memo.shape[0] >= hb[-1]
+    touched = []
+    for v in np.nonzero(hub)[0]:
+        block = memo[hb[v]:hb[v + 1]].reshape(int(deg[v]), row_words(deg[v], weighted))
+        for pos in np.nonzero(block.any(axis=1))[0]:
+            touched.append((int(v), int(pos)))
     rng = np.random.default_rng(seed)
-    pick = touched if len(touched) <= limit else rng.choice(touched, limit, replace=False)
-    hubs = np.nonzero(hub)[0]
-    owner = hubs[np.searchsorted(hb[hubs], pick, side="right") - 1]
+    pick = touched if len(touched) <= limit else [touched[i] for i in rng.choice(len(touched), limit, replace=False)]
     hinted = halves = 0
-    for r, v in zip(pick, owner):
-        pos = int(r - hb[v])
+    for v, pos in pick:
+        nsp = memo_segs(deg[v])
+        rw = row_words(deg[v], weighted)
+        row = memo[hb[v] + pos * rw:hb[v] + (pos + 1) * rw]
+        counts, hints, halfs = row[:nsp], row[nsp:2 * nsp], row[2 * nsp:3 * nsp]
         nv = og.row(v)
         t = int(nv[pos])
         nt = og.row(t)
@@ -329,36 +350,35 @@ def check_sketch_rows(og, memo, min_deg, limit=6000, seed=1):
         com = np.isin(nv, nt, assume_unique=True)
         firsts = np.arange(0, len(nv), seglen)
         want = np.add.reduceat(com.astype(np.int64), firsts) + 1
-        got = rows[r, :64]
-        assert np.array_equal(got[:nsup], want), (int(v), t, got[:nsup], want)
-        assert not got[nsup:].any() and not rows[r, 64 + nsup:128].any() and not rows[r, 128 + nsup:192].any()
+        assert np.array_equal(counts[:nsup], want), (v, t, counts[:nsup], want)
+        assert not counts[nsup:].any() and not hints[nsup:].any() and not halfs[nsup:].any()
         if weighted:
             # per segment: members' weight sum + 1, the same over the first half + 1, all
             # entries' weight sum, the same over the first half (0 where not written)
+            sums = np.ascontiguousarray(row[3 * nsp:]).view(np.uint32).astype(np.int64)
             w = og.wt[int(og.off[v]):int(og.off[v + 1])].astype(np.int64)
             cw = np.add.reduceat(np.where(com, w, 0), firsts)
             wa = np.add.reduceat(w, firsts)
             cw1 = np.array([int(np.where(com, w, 0)[a:min(a + seglen // 2, len(nv))].sum()) for a in firsts])
             wa1 = np.array([int(w[a:min(a + seglen // 2, len(nv))].sum()) for a in firsts])
-            sr = sums[r].astype(np.int64)
-            for k, want_k in ((0, cw + 1), (64, cw1 + 1), (128, wa), (192, wa1)):
-                part = sr[k:k + nsup]
-                assert np.all((part == 0) | (part == want_k)), (int(v), t, k)
-                assert not sr[k + nsup:k + 64].any()
-            assert np.all(sr[0:nsup] == cw + 1) and np.all(sr[128:128 + nsup] == wa)
+            for k, want_k in enumerate((cw + 1, cw1 + 1, wa, wa1)):
+                part = sums[k * nsp:k * nsp + nsup]
+                assert np.all((part == 0) | (part == want_k)), (v, t, k)
+                assert not sums[k * nsp + nsup:(k + 1) * nsp].any()
+            assert np.all(sums[0:nsup] == cw + 1) and np.all(sums[2 * nsp:2 * nsp + nsup] == wa)
         half = np.array([int(com[a:min(a + seglen // 2, len(nv))].sum()) for a in firsts]) + 1
-        hv = rows[r, 128:128 + nsup].astype(np.int64)
+        hv = halfs[:nsup].astype(np.int64)
         hknown = hv > 0
         halves += int(hknown.sum())
-        assert np.array_equal(hv[hknown], half[hknown]), (int(v), t, hv, half)
+        assert np.array_equal(hv[hknown], half[hknown]), (v, t, hv, half)
         hs = hint_shift(len(nt))
         lb = np.searchsorted(nt, nv[firsts], side="left")
         ub_prev = np.concatenate([[0], np.searchsorted(nt, nv[firsts[1:] - 1], side="right")])
-        h = rows[r, 64:64 + nsup].astype(np.int64)
+        h = hints[:nsup].astype(np.int64)
         known = h > 0
         hinted += int(known.sum())
-        assert np.all((ub_prev >> hs)[known] <= h[known] - 1), (int(v), t)
-        assert np.all(h[known] - 1 <= (lb >> hs)[known]), (int(v), t)
+        assert np.all((ub_prev >> hs)[known] <= h[known] - 1), (v, t)
+        assert np.all(h[known] - 1 <= (lb >> hs)[known]), (v, t)
     assert hinted > 0 and halves > 0
     return len(touched)
 
@@ -379,7 +399,7 @@ def test_pair_sketch_contents(mode, t_wg, search):
     starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
     got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=100000, t_wg=t_wg, search_ratio=search)
     torch.cuda.synchronize()
-    memo = g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192)
+    memo = g.memo.cpu().numpy().view(np.uint16)
     n = check_sketch_rows(og, memo, 41)
     say(f"[walk] sketches mode={mode}: {n} rows written")
     assert n > 1000
@@ -401,9 +421,10 @@ def test_pair_sketches_above_degree_threshold(mode):
     deg = og.degree()
     got_bytes = g.attach_memo(budget=full // 3)
     T = g.memo_min_degree
-    assert 41 < T < 2 ** 20 and got_bytes == int(deg[deg >= T].sum()) * 384 <= full // 3
+    assert full == sketch_bytes(deg, 41)
+    assert 41 < T < 2 ** 20 and got_bytes == sketch_bytes(deg, T) <= full // 3
     # the threshold is the smallest that fits
-    assert T - 1 <= 41 or int(deg[deg >= T - 1].sum()) * 384 > full // 3
+    assert T - 1 <= 41 or sketch_bytes(deg, T - 1) > full // 3
     hubs = np.argsort(deg)[-256:].astype(np.uint32)
     starts = np.concatenate([np.repeat(hubs, 16), np.arange(og.n, dtype=np.uint32)])
     want = oracle_walk(og, starts, 20, 0.25, 4.0, 8, d_rule=40)
@@ -411,14 +432,14 @@ def test_pair_sketches_above_degree_threshold(mode):
     got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=4)
     assert first_mismatch(got, want) is None
     torch.cuda.synchronize()
-    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192), T)
+    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16), T)
     assert n > 100
     g.detach_memo()
     assert g.attach_memo() == full
     got = gpu_walk(g, starts, 20, 0.25, 4.0, 8, mode=mode, sparse_ratio=4)
     assert first_mismatch(got, want) is None
     torch.cuda.synchronize()
-    assert check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192), 41) > 100
+    assert check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16), 41) > 100
     g.detach_memo()
     assert g.attach_memo(budget=0) == 0
 
@@ -552,7 +573,7 @@ def test_memo_min_refusal_leaves_the_graph_unchanged():
     got = gpu_walk(g, starts, 20, 0.25, 4.0, 9)
     want = oracle_walk(og, starts, 20, 0.25, 4.0, 9, d_rule=40)
     assert first_mismatch(got, want) is None, first_mismatch(got, want)
-    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 192), T)
+    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16), T)
     assert n > 50
     g.detach_memo()
     del small
@@ -577,7 +598,7 @@ def test_sketches_persist_across_calls_and_clear(mode):
         assert first_mismatch(got, want) is None, (p, q, first_mismatch(got, want))
     memo = g.memo.cpu().numpy().view(np.uint16)
     assert np.count_nonzero(memo) > 0
-    assert check_sketch_rows(og, memo.reshape(-1, 192), 41) > 100
+    assert check_sketch_rows(og, memo, 41) > 100
     g.memo_clear()
     torch.cuda.synchronize()
     assert int(torch.count_nonzero(g.memo).item()) == 0
@@ -605,7 +626,7 @@ def test_weighted_pair_sketches(mode):
         want = oracle_walk(og, starts, 20, p, q, seed, d_rule=40)
         assert first_mismatch(got, want) is None, (p, q, first_mismatch(got, want))
     torch.cuda.synchronize()
-    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16).reshape(-1, 704), 41)
+    n = check_sketch_rows(og, g.memo.cpu().numpy().view(np.uint16), 41)
     assert n > 100
     g.detach_memo()
 

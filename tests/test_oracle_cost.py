@@ -192,13 +192,25 @@ def test_memo_closed_forms_by_hand():
     assert O.memo_cold_lines(g.off, 5, 0, weighted=True) == 12
     # at leaf 5 after the centre: merge 1 + 13 = 14, search 13 + 200 x 1 = 213
     assert O.memo_cold_lines(g.off, 0, 5) == 14
-    # warm at degree 100000 after degree 3000: 196 tiles, segments of 4 x 512, half 1024
-    # entries (64 lines), ceil(3000 x 1024 / 100000) = 31 entries of N(t) (2 lines), row 6
+    # warm at degree 100000 after degree 3000: 196 tiles, segments of 4 x 512 (49, a row of 50
+    # x 6 = 300 bytes: 5 lines), half 1024 entries (64 lines), ceil(3000 x 1024 / 100000) = 31
+    # entries of N(t) (2 lines)
     off = np.array([0, 100000, 103000], dtype=np.uint64)
-    assert O.memo_warm_lines(off, 1, 0) == 72
-    # degree 600 after 100: segments of 512, half 256 entries (16 lines), 43 entries (3 lines)
+    assert O.memo_warm_lines(off, 1, 0) == 71
+    # degree 600 after 100: two segments of 512 (a 12-byte row: 1 line), half 256 entries (16
+    # lines), 43 entries (3 lines)
     off = np.array([0, 600, 700], dtype=np.uint64)
-    assert O.memo_warm_lines(off, 1, 0) == 25
+    assert O.memo_warm_lines(off, 1, 0) == 20
+
+
+def test_memo_row_bytes_by_hand():
+    # 6 bytes per segment (22 weighted), segments of whole 512-entry tiles, at most 64 of them,
+    # rounded up to an even count
+    assert [O.memo_row_bytes(d) for d in (1, 512, 1025, 3000, 32768)] == [12, 12, 24, 36, 384]
+    # 65 tiles: two per segment, 33 segments, 34 in the row; 196 tiles: four per segment, 49
+    assert O.memo_row_bytes(32769) == 6 * 34 and O.memo_row_bytes(100000) == 6 * 50
+    assert O.memo_row_bytes(127 * 512 * 64) == 384 and O.memo_row_bytes(127 * 512 * 64, True) == 1408
+    assert O.memo_row_bytes(600, True) == 44 and O.memo_row_bytes(100000, True) == 22 * 50
 
 
 def test_memo_pass_bytes_by_hand():
@@ -207,7 +219,7 @@ def test_memo_pass_bytes_by_hand():
     out = np.array([[5, 0, 7, 0, 5], [9, 0, 5, S, S], [7, 0, 7, 0, 7]], dtype=np.uint32)
     # hub moves (at the centre, s >= 1): row 0 s = 1, 3; row 1 s = 1; row 2 s = 1, 3 -> 5.
     # other moves: row 0 s = 0, 2; row 1 s = 0; row 2 s = 0, 2 -> 5.
-    # At the centre after a leaf the summary would cost 20 lines (row 6, half segment of 200
+    # At the centre after a leaf the summary would cost 15 lines (row 1, half segment of 200
     # entries 13, one entry of N(t) 1) against 5 lines for searching the leaf's one
     # neighbour: every move takes the search (5 lines + off 1) and no intersection is kept
     cold = dict(hub_bytes=5 * (6 * 64 + 4), hub_moves=5, other_moves=5, intersections=0, warm_moves=0)
@@ -222,13 +234,14 @@ def test_memo_pass_bytes_with_summaries_by_hand():
     off = np.array([0, 100000, 103000, 103001], dtype=np.uint64)
     out = np.array([[2, 0, 1, 0, 1, 0]], dtype=np.uint32)
     # s = 0 at vertex 2: another move.
-    # s = 1 at 0 after 2: summary 6 + 64 + 1 = 71 lines, search 1 + 1 x 13 = 14: 14 lines
-    # s = 2 at 1 after 0: summary 6 + 16 (half of a 512 segment) + 534 (8534 entries of
-    #   N(0)) = 556 lines, cold min(6250 + 188, 6250 + 100000 x 8) = 6438: 556; key {0, 1}
-    # s = 3 at 0 after 1: summary 72 (as in the closed forms), cold 6438: 72; key {0, 1}
-    # s = 4 at 1 after 0: 556; key {0, 1}
+    # s = 1 at 0 after 2: summary 5 + 64 + 1 = 70 lines, search 1 + 1 x 13 = 14: 14 lines
+    # s = 2 at 1 after 0: summary 1 (six segments: 36 bytes) + 16 (half of a 512 segment) +
+    #   534 (8534 entries of N(0)) = 551 lines, cold min(6250 + 188, 6250 + 100000 x 8) = 6438:
+    #   551; key {0, 1}
+    # s = 3 at 0 after 1: summary 71 (as in the closed forms), cold 6438: 71; key {0, 1}
+    # s = 4 at 1 after 0: 551; key {0, 1}
     # one intersection {0, 1}: merge 6250 + 188 = 6438, search 188 + 3000 x 13 = 39188
-    hub = (1 + 14) * 64 + 4 + (1 + 556) * 64 + 4 + (1 + 72) * 64 + 4 + (1 + 556) * 64 + 4 + 6438 * 64
+    hub = (1 + 14) * 64 + 4 + (1 + 551) * 64 + 4 + (1 + 71) * 64 + 4 + (1 + 551) * 64 + 4 + 6438 * 64
     r = O.memo_pass_bytes(off, out, 5, d_rule=10)
     assert r == dict(hub_bytes=hub, hub_moves=4, other_moves=1, intersections=1, warm_moves=3)
     # no summaries: 14, then 6438 for each of the others
@@ -238,25 +251,26 @@ def test_memo_pass_bytes_with_summaries_by_hand():
     # vertex 1 keeps no summary (threshold 3001): its moves pay 6438, and the summary of
     # vertex 0 serves the directed key (0, 1) only
     r = O.memo_pass_bytes(off, out, 5, d_rule=10, memo_min=3001)
-    assert r == dict(hub_bytes=(1 + 14) * 64 + 4 + 2 * ((1 + 6438) * 64 + 4) + (1 + 72) * 64 + 4 + 6438 * 64,
+    assert r == dict(hub_bytes=(1 + 14) * 64 + 4 + 2 * ((1 + 6438) * 64 + 4) + (1 + 71) * 64 + 4 + 6438 * 64,
                      hub_moves=4, other_moves=1, intersections=1, warm_moves=1)
 
 
 def test_memo_pass_bytes_weighted_by_hand():
-    # the same rows, weighted: a summary row is 22 lines (four 32-bit sums per segment beside the
-    # 6 lines of counts and hints), the half segment's weights are read too, every key is
+    # the same rows, weighted: a summary row holds four 32-bit sums per segment beside the counts
+    # and hints (22 bytes per segment: 1100 bytes, 18 lines, for the 50 of vertex 0; 132 bytes,
+    # 3 lines, for the 6 of vertex 1), the half segment's weights are read too, every key is
     # directed (v, t), and building a summary costs the directed cold evaluation, weights of
     # N(v) included (vertex 0: 100000 weights, 3125 lines; vertex 1: bytes 200000..205999 of
     # wt, 94 lines).
     off = np.array([0, 100000, 103000, 103001], dtype=np.uint64)
     out = np.array([[2, 0, 1, 0, 1, 0]], dtype=np.uint32)
-    assert O.memo_warm_lines(off, 1, 0, weighted=True) == 22 + 64 + 32 + 2
-    # s = 1 at 0 after 2: summary 22 + 64 + 32 + 1 = 119 against cold min(6250 + 1, 1 + 13) + 3125
-    #   = 3139: 119, key (0, 2)
-    # s = 2 at 1 after 0: 22 + 16 + 8 + 534 = 580 against min(188 + 6250, 6250 + 800000) + 94
-    #   = 6532: 580, key (1, 0); s = 4 the same key again
-    # s = 3 at 0 after 1: 120 against min(6250 + 188, 188 + 39000) + 3125 = 9563: 120, key (0, 1)
-    hub = ((1 + 119) + (1 + 580) + (1 + 120) + (1 + 580)) * 64 + 4 * 4 + (3139 + 6532 + 9563) * 64
+    assert O.memo_warm_lines(off, 1, 0, weighted=True) == 18 + 64 + 32 + 2
+    # s = 1 at 0 after 2: summary 18 + 64 + 32 + 1 = 115 against cold min(6250 + 1, 1 + 13) + 3125
+    #   = 3139: 115, key (0, 2)
+    # s = 2 at 1 after 0: 3 + 16 + 8 + 534 = 561 against min(188 + 6250, 6250 + 800000) + 94
+    #   = 6532: 561, key (1, 0); s = 4 the same key again
+    # s = 3 at 0 after 1: 116 against min(6250 + 188, 188 + 39000) + 3125 = 9563: 116, key (0, 1)
+    hub = ((1 + 115) + (1 + 561) + (1 + 116) + (1 + 561)) * 64 + 4 * 4 + (3139 + 6532 + 9563) * 64
     r = O.memo_pass_bytes(off, out, 5, d_rule=10, weighted=True)
     assert r == dict(hub_bytes=hub, hub_moves=4, other_moves=1, intersections=3, warm_moves=4)
 

@@ -70,7 +70,13 @@ MUTATIONS = [
      "ph(seed, wid, col, x, 3, r);", "ph(seed, wid, x, col, 3, r);"),
     # the memo-aware model
     ("memo: summary row not charged",
-     "return 6 + (4 * h + 63) / 64 + (4 * ht + 63) / 64;", "return (4 * h + 63) / 64 + (4 * ht + 63) / 64;"),
+     "    return row + (4 * h + 63) / 64 + (4 * ht + 63) / 64;", "    return (4 * h + 63) / 64 + (4 * ht + 63) / 64;"),
+    ("memo: summary row segments not rounded up to even",
+     "    segs = (segs + 1) & ~1ull;", "    segs = segs;"),
+    ("memo: summary row of 64 segments at every degree",
+     "    uint64_t segs = (tiles + per - 1) / per;", "    uint64_t segs = 64;"),
+    ("memo: tiles per summary segment off by one",
+     "    uint64_t per = tiles ? (tiles + 63) / 64 : 1;", "    uint64_t per = tiles ? (tiles + 63) / 64 + 1 : 1;"),
     ("memo: one summary per direction of a pair",
      "key = t < v ? ((uint64_t)t << 32) | v : ((uint64_t)v << 32) | t;", "key = ((uint64_t)v << 32) | t;"),
     ("memo: intersection charged on every move",
@@ -82,7 +88,7 @@ MUTATIONS = [
     ("memo: weighted summaries shared by both directions",
      "if (!weighted && or_memo_keeps(dt, memo_min))", "if (or_memo_keeps(dt, memo_min))"),
     ("memo: weighted summary row charged as unweighted",
-     "if (weighted) return 22 + (4 * h + 63) / 64", "if (weighted) return 6 + (4 * h + 63) / 64"),
+     "    return (weighted ? 22 : 6) * segs;", "    return 6 * segs;"),
     ("memo: summary read even when dearer",
      "            if (warm < cold) {", "            if (warm < cold + 1000000) {"),
     # the Skip-gram step that consumes the walks
