@@ -535,12 +535,23 @@ __device__ uint64_t dense_chunk_sum(const uint16_t *__restrict__ W, const JobCtx
     return wave_sum(s);
 }
 
+// The weights of lane l's run of a tile, N(v)[j0 + XPL*l, +XPL) (0 past cnt),
+// loaded before the tile's flags are formed so that their reads overlap the
+// merge's instead of following it.
+__device__ __forceinline__ void tile_run_weights(const uint16_t *__restrict__ W, uint32_t j0, uint32_t cnt,
+                                                 uint32_t (&w)[XPL])
+{
+    const uint32_t i0 = (uint32_t)lane_id() * XPL;
+#pragma unroll
+    for (int e = 0; e < XPL; ++e) w[e] = W && i0 + e < cnt ? W[j0 + i0 + e] : (W ? 0u : 1u);
+}
+
 // First index of the tile whose running prefix (base + partial) exceeds r,
 // or SENT (base then holds the prefix after the tile).  Lane l takes the run
 // of entries [XPL*l, XPL*l + XPL): one 32-bit wave scan of the run sums (a
 // tile sums to at most 512 * 65535 * 16 < 2^32) finds the lane whose run
 // crosses r, and that lane walks its run.
-__device__ uint32_t dense_chunk_locate(const uint16_t *__restrict__ W, const JobCtx &J, uint32_t pos_t,
+__device__ uint32_t dense_chunk_locate(const uint32_t (&wrun)[XPL], const JobCtx &J, uint32_t pos_t,
                                        const HubLds &L, uint32_t j0, uint32_t cnt, uint64_t &base, uint64_t r)
 {
     const int l = lane_id();
@@ -551,7 +562,7 @@ __device__ uint32_t dense_chunk_locate(const uint16_t *__restrict__ W, const Job
 #pragma unroll
     for (int e = 0; e < XPL; ++e) {
         const uint32_t i = i0 + e;
-        const uint32_t w = i < cnt ? (W ? W[j0 + i] : 1u) : 0u;
+        const uint32_t w = i < cnt ? wrun[e] : 0u;
         const uint32_t m = (j0 + i == pos_t) ? J.A_ret : (((f8 >> (8 * e)) & 0xFF) ? A_COM : J.A_out);
         pi[e] = w * m;
         run += pi[e];
@@ -603,7 +614,7 @@ struct TileW {
     uint32_t all, com, all1, com1;
 };
 
-__device__ __forceinline__ TileW tile_weights(const uint16_t *__restrict__ W, const HubLds &L, uint32_t j0, uint32_t cnt)
+__device__ __forceinline__ TileW tile_weights(const uint32_t (&wrun)[XPL], const HubLds &L, uint32_t cnt)
 {
     const int l = lane_id();
     const uint32_t i0 = (uint32_t)l * XPL;
@@ -611,7 +622,7 @@ __device__ __forceinline__ TileW tile_weights(const uint16_t *__restrict__ W, co
     uint32_t a = 0, c = 0;
 #pragma unroll
     for (int e = 0; e < XPL; ++e) {
-        const uint32_t w = i0 + e < cnt ? W[j0 + i0 + e] : 0u;
+        const uint32_t w = i0 + e < cnt ? wrun[e] : 0u;
         a += w;
         c += ((f8 >> (8 * e)) & 0xFF) ? w : 0u;
     }
@@ -740,6 +751,8 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
             for (uint32_t sub = sp * G; sub < sub_end; ++sub) {
                 const uint32_t j0 = sub * TX;
                 const uint32_t cnt = dv - j0 < (uint32_t)TX ? dv - j0 : (uint32_t)TX;
+                uint32_t wrun[XPL];
+                if (W) tile_run_weights(W, j0, cnt, wrun);
                 uint32_t c;
                 if (srch) {
                     uint32_t lb0;
@@ -750,7 +763,7 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
                 }
                 const uint32_t ct = c & 0xFFFFu;
                 if (W) {
-                    const TileW tw = tile_weights(W, L, j0, cnt);
+                    const TileW tw = tile_weights(wrun, L, cnt);
                     sum += wseg_pi(J, tw.all, tw.com, pos_t >= j0 && pos_t - j0 < cnt ? wt_t : 0u);
                     sw += tw.all;
                     scw += tw.com;
@@ -860,13 +873,15 @@ __device__ uint32_t hub_dense(const Exec &E, const JobCtx &J, const WS &st, HubL
     const RevSketch none = {};
     for (uint32_t j0 = xa; j0 < xb; j0 += TX) {
         const uint32_t cnt = xb - j0 < (uint32_t)TX ? xb - j0 : (uint32_t)TX;
+        uint32_t wrun[XPL];
+        tile_run_weights(W, j0, cnt, wrun);
         if (srch) {
             uint32_t lb0;
             search_flags(X, Y, ypos, yend, np, B, L, j0, cnt, none, lb0);
         } else {
             dense_flags(X, Y, td, L, j0, cnt, ypos, none);
         }
-        const uint32_t j = dense_chunk_locate(W, J, pos_t, L, j0, cnt, base, r);
+        const uint32_t j = dense_chunk_locate(wrun, J, pos_t, L, j0, cnt, base, r);
         if (j != SENT) xj = L.a.d.xs[j - j0];  // the chosen neighbour, still in the tile
         wave_lds_sync();
         if (j != SENT) return j;
@@ -1224,7 +1239,9 @@ __device__ __forceinline__ uint32_t block_dense(const Exec &E, const JobCtx &J, 
             after += B.part[k];
         }
         if (has && before <= r && before + tsum > r) {
-            const uint32_t j = dense_chunk_locate(W, J, pos_t, L, j0, cnt, before, r);
+            uint32_t wrun[XPL];
+            tile_run_weights(W, j0, cnt, wrun);
+            const uint32_t j = dense_chunk_locate(wrun, J, pos_t, L, j0, cnt, before, r);
             if (l == 0) B.ans = j;
         }
         wave_lds_sync();
