@@ -34,7 +34,7 @@ constexpr int SG_DIM = 128;               // embedding dimension
 constexpr int SG_MAXC = 96;               // walk positions per walk (L + 1 <= 96)
 constexpr int SG_MAXNEG = 64;             // shared negatives per walk
 constexpr int SG_T = SG_MAXC + SG_MAXNEG; // targets: walk positions, then negatives
-constexpr int SG_BLOCK = 256;             // four wavefronts
+constexpr int SG_BLOCK = 512;             // eight wavefronts, one product unit each
 constexpr int LD_V = SG_DIM + 8;          // LDS row stride (bf16) of V[c][d] and T[t][d], padded against bank conflicts
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -106,29 +106,50 @@ __device__ __forceinline__ bf16x8 lds_rows8(const __bf16 *M, int r0, int d0)
     return b;
 }
 
-__device__ __forceinline__ float softplus(float x) { return x > 0.f ? x + log1pf(expf(-x)) : log1pf(expf(x)); }
-
-__device__ __forceinline__ float sigmoid(float x) { return 1.f / (1.f + expf(-x)); }
-
 // Gradient coefficient of the logit z of (center c, target t), adding its
 // loss term to `loss`: context pairs (a walk position within the window)
-// sigmoid(z) - 1, negatives neg_weight * sigmoid(z), anything else 0.
+// sigmoid(z) - 1, negatives neg_weight * sigmoid(z), anything else 0.  All
+// come from e = exp(-|z|) and r = 1 / (1 + e) without cancellation:
+// sigmoid(z) is r for z >= 0 and e r below, sigmoid(z) - 1 is -e r and -r,
+// and softplus(-z) = max(-z, 0) + log(1 + e), softplus(z) = max(z, 0) +
+// log(1 + e).  The hardware exponential and reciprocal leave a relative error
+// of about (|z| + 4) 2^-24, far below the bf16 rounding of the logits and of
+// the coefficients themselves.
 __device__ __forceinline__ float sg_coef(const SgArgs &A, uint32_t len, uint32_t c, uint32_t t, float z, float &loss)
 {
     if (c >= len) return 0.f;
+    bool ctx = false;
     if (t < (uint32_t)SG_MAXC) {
         const uint32_t dist = c > t ? c - t : t - c;
-        if (t < len && dist >= 1 && dist <= A.window) {
-            loss += softplus(-z);
-            return sigmoid(z) - 1.f;
-        }
+        if (!(t < len && dist >= 1 && dist <= A.window)) return 0.f;
+        ctx = true;
+    } else if (t - SG_MAXC >= A.nneg) {
         return 0.f;
     }
-    if (t - SG_MAXC < A.nneg) {
-        loss += A.neg_weight * softplus(z);
-        return A.neg_weight * sigmoid(z);
+    const float e = __expf(-fabsf(z));
+    const float r = __builtin_amdgcn_rcpf(1.f + e);
+    const float er = e * r;
+    // log(1 + e): the series where 1 + e would round away most of e
+    const float l1 = e < 0x1p-12f ? e * (1.f - 0.5f * e) : __logf(1.f + e);
+    if (ctx) {
+        loss += fmaxf(-z, 0.f) + l1;
+        return z >= 0.f ? -er : -r;
     }
-    return 0.f;
+    loss += A.neg_weight * (fmaxf(z, 0.f) + l1);
+    return A.neg_weight * (z >= 0.f ? r : er);
+}
+
+// Whether center block cb (centers 32 cb ..) and target block tb (walk
+// positions 32 tb .. for tb < 3, negatives 32 (tb - 3) .. above) hold a pair
+// with a nonzero coefficient; the products skip blocks without one.
+__device__ __forceinline__ bool sg_block_live(const SgArgs &A, uint32_t len, uint32_t cb, uint32_t tb)
+{
+    if (32 * cb >= len) return false;
+    if (tb < (uint32_t)(SG_MAXC / 32)) {
+        if (32 * tb >= len) return false;
+        return 32 * tb <= 32 * cb + 31 + A.window && 32 * tb + 31 + A.window >= 32 * cb;
+    }
+    return 32 * (tb - SG_MAXC / 32) < A.nneg;
 }
 
 __global__ __launch_bounds__(SG_BLOCK, 2) void k_sg_walks(SgArgs A)
@@ -157,7 +178,7 @@ __global__ __launch_bounds__(SG_BLOCK, 2) void k_sg_walks(SgArgs A)
     // rows are loaded together, so their latencies overlap instead of adding up
     constexpr int NROWS = SG_MAXC + SG_T;                // 256 rows
     constexpr int RSTEP = SG_BLOCK / 32;                 // rows per pass of the block
-    constexpr int GATHER = 32;                           // loads in flight per thread (one batch)
+    constexpr int GATHER = 16;                           // loads in flight per thread (one batch)
     static_assert(NROWS % (RSTEP * GATHER) == 0, "rows split evenly into gather batches");
     const int q = tid & 31;
     for (int r0 = tid / 32; r0 < NROWS; r0 += RSTEP * GATHER) {
@@ -187,8 +208,8 @@ __global__ __launch_bounds__(SG_BLOCK, 2) void k_sg_walks(SgArgs A)
         }
     }
     __syncthreads();
-    // Eight units over the four wavefronts (unit wv and wv + 4), each for all
-    // four 32-wide column blocks of the 128 dimensions:
+    // Eight units, one per wavefront (unit wv), each for all four 32-wide
+    // column blocks of the 128 dimensions:
     //   units 0..2: center gradients dV = G T of center block ci = u: the
     //     logits of the block, transposed (Z^T = T V^T, lanes hold centers),
     //     give the A operands directly, T rows the B operands;
@@ -196,7 +217,9 @@ __global__ __launch_bounds__(SG_BLOCK, 2) void k_sg_walks(SgArgs A)
     //     the logits Z = V T^T (lanes hold targets) give the A operands, V
     //     rows the B operands; these units also add up the loss.
     float loss = 0.f;
-    for (int u = wv; u < 8; u += 4) {
+    static_assert(SG_BLOCK / WAVE == 8, "one product unit per wavefront");
+    {
+        const int u = wv;
         const bool centers = u < 3;
         const int blk = centers ? u : u - 3;
         f32x16 acc[4];
@@ -204,6 +227,7 @@ __global__ __launch_bounds__(SG_BLOCK, 2) void k_sg_walks(SgArgs A)
         for (int dj = 0; dj < 4; ++dj) acc[dj] = f32x16{};
         const int nk = centers ? SG_T / 32 : SG_MAXC / 32;  // 32-row blocks of the contraction
         for (int kb = 0; kb < nk; ++kb) {
+            if (!(centers ? sg_block_live(A, len, blk, kb) : sg_block_live(A, len, kb, blk))) continue;
             // logits tile: rows kb-block of the other side, columns (lanes) this unit's block
             const f32x16 z = centers ? tile_dot<SG_DIM>(S.T, LD_V, 32 * kb, S.V, LD_V, 32 * blk)
                                      : tile_dot<SG_DIM>(S.V, LD_V, 32 * kb, S.T, LD_V, 32 * blk);
@@ -246,7 +270,8 @@ __global__ __launch_bounds__(SG_BLOCK, 2) void k_sg_walks(SgArgs A)
     if (l == 0) S.wloss[wv] = loss;
     __syncthreads();
     if (tid == 0) {
-        const float s = S.wloss[0] + S.wloss[1] + S.wloss[2] + S.wloss[3];
+        float s = 0.f;
+        for (int w = 0; w < SG_BLOCK / WAVE; ++w) s += S.wloss[w];
         if (s != 0.f) atomicAdd(A.loss, (double)s);
     }
 }

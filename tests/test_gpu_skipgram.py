@@ -5,7 +5,9 @@ Bound (per element, from the rounding the kernel performs): the table values are
 rounded to bf16 (unit roundoff u = 2^-9), so each logit z = sum_d v_d t_d carries
 at most (2u + u^2 + 128 * 2^-24) * sum_d |v_d t_d| of error; a coefficient
 (sigmoid, derivative at most 1/4, times neg_weight for negatives) at most a
-quarter of that, plus 2^-20 |g| for the fp32 exponential; the coefficient is
+quarter of that, plus 2^-20 |g| for the hardware exponential and reciprocal
+(about (|z| + 4) 2^-24 relative; where |z| > 12 the logit term is larger by
+far); the coefficient is
 rounded to bf16 again (u); each gradient element sum_t g_t x_t then errs by at
 most sum_t (dg_t + u |g_t|) |x_t| (1 + u) + (u + K 2^-24) sum_t |g_t x_t|, and
 the fp32 atomic sums over a row's contributions by 2^-20 of their absolute sum.
