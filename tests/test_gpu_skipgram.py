@@ -141,3 +141,82 @@ def test_skipgram_two_steps_keep_the_workspace_clean():
         s = (0.05 / np.maximum(occ, 1.0))[:, None]
         tol = s * b + 2.0 ** -23 * (np.abs(w0) + s * np.abs(g)) + 1e-12
         assert (np.abs(got - want) <= tol).all()
+
+
+@pytest.mark.timeout(600)
+def test_skipgram_full_size_batch_sampled_rows():
+    # The bench's step shape: the first 65,536 walks of the scale-20 weighted workload (80 moves,
+    # p = 1, q = 1/2), window 10, 64 negatives, on the full 2^20-row tables. Rows are compared for
+    # a seeded sample of vertices, each against the oracle's step over exactly the walks that touch
+    # it (its update depends on nothing else). The oracle draws negatives by a linear scan of the
+    # noise table, too slow for all 4.2 M draws, so the walks that draw a sampled vertex are found
+    # from the device's draws; the oracle redraws the negatives of every walk it steps over plus
+    # 256 seeded-random others, and they must equal the device's.
+    from paper_1805_00280_amd import workloads as WL
+    torch = torch_cuda()
+    w = WL.C2
+    batch, window, nneg, lr, seed, stp = 1 << 16, 10, 64, 0.025, 11, 3
+    og = oracle_rmat(*w.rmat_args(), w.weighted)
+    say(f"[sgns-full] oracle walks of {batch} starts")
+    walks = oracle_walk(og, np.arange(batch, dtype=np.uint32), w.L, w.p, w.q, w.seed)
+    rng = np.random.default_rng(21)
+    n, D = og.n, 128
+    win = (rng.standard_normal((n, D)) * 0.12).astype(np.float32)
+    wout = (rng.standard_normal((n, D)) * 0.12).astype(np.float32)
+    cum = noise_table(og)
+    sg = P.SkipGram(n, torch.from_numpy(win).cuda(), torch.from_numpy(wout).cuda(),
+                    torch.from_numpy(cum.view(np.int64)).cuda(), window=window, negatives=nneg, lr=lr, seed=seed,
+                    max_walks=batch)
+    lam = sg.prm.neg_weight
+    negs_gpu = sg.negatives(batch, walk_base=0, step=stp).cpu().numpy().view(np.uint32)
+    say("[sgns-full] device step")
+    sg.step(torch.from_numpy(np.ascontiguousarray(walks).view(np.int32)).cuda(), walk_base=0, step=stp)
+    torch.cuda.synchronize()
+    gwin, gwout = sg.win.cpu().numpy(), sg.wout.cpu().numpy()
+    # which walks touch each vertex as a center (win) or as a target (wout)
+    lens = (walks != O.SENT).sum(1)
+    pos_mask = np.arange(walks.shape[1])[None, :] < lens[:, None]
+    assert np.array_equal(pos_mask, walks != O.SENT), "rows end at their first sentinel"
+    wid_pos = np.repeat(np.arange(batch), lens)
+    v_pos = walks[pos_mask].astype(np.int64)
+    wid_neg = np.repeat(np.arange(batch), nneg)
+    v_neg = negs_gpu.reshape(-1).astype(np.int64)
+    occ = np.bincount(v_pos, minlength=n) * 2 + np.bincount(v_neg, minlength=n)
+    cand = np.nonzero((occ > 0) & (occ <= 64))[0]
+    sample = rng.choice(cand, size=96, replace=False)
+    pop = np.nonzero((occ > 64) & (occ <= 512))[0]  # a few busier rows, with a bounded walk count
+    sample = np.concatenate([sample, rng.choice(pop, size=min(4, len(pop)), replace=False)])
+    in_s = np.zeros(n, dtype=bool)
+    in_s[sample] = True
+    sub = np.unique(np.concatenate([wid_pos[in_s[v_pos]], wid_neg[in_s[v_neg]]]))
+    extra = np.setdiff1d(rng.choice(batch, size=256, replace=False), sub)
+    say(f"[sgns-full] {len(sample)} sampled vertices touched by {len(sub)} walks; oracle negatives of "
+        f"{len(sub) + len(extra)} walks")
+    negs = {}
+    for i in np.concatenate([sub, extra]):
+        negs[int(i)] = SG.negatives(cum, seed, int(i), 1, nneg, stp)[0]
+        assert np.array_equal(negs[int(i)], negs_gpu[i]), f"negatives of walk {i} differ from the oracle's"
+    # the oracle's step over those walks, on the rows they use, renumbered
+    sw = walks[sub]
+    sn = np.stack([negs[int(i)] for i in sub])
+    used = np.unique(np.concatenate([sw[pos_mask[sub]].astype(np.int64), sn.reshape(-1).astype(np.int64)]))
+    loc = np.full(n, -1, dtype=np.int64)
+    loc[used] = np.arange(len(used))
+    lw = np.full(sw.shape, O.SENT, dtype=np.uint32)
+    lw[pos_mask[sub]] = loc[sw[pos_mask[sub]]].astype(np.uint32)
+    ln = loc[sn].astype(np.uint32)
+    owin, owout, _, ogin, ogout, ocin, ocout = SG.step(win[used], wout[used], lw, ln, window, lam, lr)
+    bi, bo, _ = bounds(win[used], wout[used], lw, ln, window, lam)
+    ls = loc[sample]
+    checked = 0
+    for got, want, b, g, w0, oc, name in ((gwin[sample], owin[ls], bi[ls], ogin[ls], win[sample], ocin[ls], "win"),
+                                          (gwout[sample], owout[ls], bo[ls], ogout[ls], wout[sample], ocout[ls],
+                                           "wout")):
+        s = (lr / np.maximum(oc, 1.0))[:, None]
+        tol = s * b + 2.0 ** -23 * (np.abs(w0) + s * np.abs(g)) + 1e-12
+        err = np.abs(got.astype(np.float64) - want)
+        worst = float((err / tol).max())
+        say(f"[sgns-full] {name}: {int((oc > 0).sum())} sampled rows updated, max error / bound {worst:.3f}")
+        assert worst <= 1.0, f"{name} outside the derived bound"
+        checked += int((oc > 0).sum())
+    assert checked >= len(sample)
