@@ -249,6 +249,7 @@ struct n2v_graph {
     bool has_tuned;
     n2v_exec_opts tuned;
     uint64_t hub_words;     // sketch words of the rows of degree > d_rule
+    uint64_t hub_entries;   // entries of the rows of degree > d_rule
     uint64_t memo_words;    // sketch words of the rows of degree >= dg.memo_min
     void *scan;             // scan scratch of the graph's workspace
     unsigned long long *hist;  // 64 words of the graph's workspace for degree statistics

@@ -125,6 +125,33 @@ __global__ __launch_bounds__(256) void k_deg_hist(const uint64_t *__restrict__ o
     if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
+// Entries of the rows of degree >= dmin (per-block reduction, one atomic
+// per block).
+__global__ __launch_bounds__(256) void k_deg_entries_ge(const uint64_t *__restrict__ off, uint32_t n, uint64_t dmin,
+                                                        unsigned long long *__restrict__ out)
+{
+    unsigned long long acc = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint64_t d = off[v + 1] - off[v];
+        if (d >= dmin) acc += d;
+    }
+    acc = wave_sum(acc);
+    __shared__ unsigned long long part[256 / WAVE];
+    if (lane_id() == 0) part[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < 256 / WAVE; ++i) t += part[i];
+        if (t) atomicAdd(out, t);
+    }
+}
+
+__global__ void k_zero_u64w(unsigned long long *p, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 // Sketch words of the rows of degree >= dmin (per-block reduction, one
 // atomic per block).
 __global__ __launch_bounds__(256) void k_deg_sum_ge(const uint64_t *__restrict__ off, uint32_t n, uint64_t dmin,
@@ -256,7 +283,12 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
     int rc = exclusive_scan_u64(L.hbase, (uint64_t)n + 1, L.scan, st);
     if (rc) return rc;
     uint64_t hub_words = 0;
+    unsigned long long hub_entries = 0;
     uint32_t wrange[2] = {0, 0};
+    hipLaunchKernelGGL(k_zero_u64w, dim3(1), dim3(64), 0, st, L.hist, 1u);
+    hipLaunchKernelGGL(k_deg_entries_ge, dim3(grid_for_waves(n)), dim3(256), 0, st, off, n, memo_min, L.hist);
+    N2V_HIP(hipGetLastError());
+    N2V_HIP(hipMemcpyAsync(&hub_entries, L.hist, sizeof(hub_entries), hipMemcpyDeviceToHost, st));
     N2V_HIP(hipMemcpyAsync(&hub_words, L.hbase + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     N2V_HIP(hipMemcpyAsync(wrange, L.status + 2, sizeof(wrange), hipMemcpyDeviceToHost, st));
     N2V_HIP(hipStreamSynchronize(st));
@@ -272,6 +304,7 @@ extern "C" int n2v_graph_create(const uint64_t *off, const uint32_t *adj, const 
     g->dg.hbase = L.hbase;
     g->dg.memo = nullptr;
     g->hub_words = hub_words;
+    g->hub_entries = hub_entries;
     g->memo_words = hub_words;
     g->scan = L.scan;
     g->memo_bytes = 0;
@@ -333,11 +366,6 @@ extern "C" int n2v_graph_memo_bytes(const n2v_graph *g, size_t *bytes)
 }
 
 namespace {
-
-__global__ void k_zero_u64w(unsigned long long *p, uint32_t n)
-{
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
-}
 
 // Sketch words of the rows of degree >= dmin, through the graph's statistics
 // words (synchronous on the default stream).

@@ -1393,7 +1393,6 @@ struct JobTable {
 
 // ---------------------------------------------------------- persistent
 constexpr int PBLOCK = 256;
-constexpr int THREAD_ITERS = 8;
 constexpr int POOL = 256;  // most walks a wavefront claims per atomic
 
 // Walk slot of one lane, kept in LDS between the thread and wave phases so
@@ -1514,7 +1513,7 @@ __global__ __launch_bounds__(PBLOCK, 5) void k_persistent(Exec E_arg, Src S)
                 pool_next += took < avail ? took : avail;
             }
             if (ballot(live) == 0) break;
-            for (int it = 0; it < THREAD_ITERS; ++it) {
+            for (uint32_t it = 0; it < E.thread_iters; ++it) {
                 if (live && !pend && st.vd > tw) pend = true;
                 const bool can = live && !pend;
                 if (ballot(can) == 0) break;
@@ -2041,6 +2040,12 @@ void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E)
     E->t_wg = o.t_wg < g->dg.d_rule ? g->dg.d_rule : o.t_wg;
     E->search_ratio = o.search_ratio;
     E->sparse_ratio = o.sparse_ratio < 1 ? 1 : o.sparse_ratio;
+    // Where hub rows hold a large share of the entries (so of the visits), a
+    // lane's walk soon reaches one and waits while the other lanes go on: two
+    // rejection moves per lane before the wave serves its pending walks.
+    // Otherwise eight, since each return to the wave phase reloads the lanes'
+    // vertex records.
+    E->thread_iters = g->hub_entries * 50 >= g->dg.m && g->hub_entries ? 2u : 8u;
 }
 
 PlainKey plain_key(const Exec &E, const OneJob &S, const void *ws, uint32_t hub_blocks, bool W, bool C)
@@ -2067,6 +2072,7 @@ PlainKey plain_key(const Exec &E, const OneJob &S, const void *ws, uint32_t hub_
     k.put2(E.t_wave, E.t_sparse);
     k.put2(E.sparse_ratio, E.t_wg);
     k.put2(E.search_ratio, hub_blocks);
+    k.put2(E.thread_iters, 0u);
     k.put(E.cursor);
     k.put(S.c.out);
     k.put(S.c.cnt);

@@ -15,6 +15,7 @@ struct Exec {
     uint32_t sparse_ratio;  // cost weight of one search against streaming
     uint32_t t_wg;          // plain form: dense hub moves at degree > t_wg use a whole workgroup
     uint32_t search_ratio;  // dense merges search N(v) in N(t) when N(t)'s range is longer by more
+    uint32_t thread_iters;  // persistent form: rejection moves a lane takes before the wave serves pending walks
     uint32_t *cursor;       // walk counter of a single-job launch (taken per launch, zeroed before it)
 };
 
