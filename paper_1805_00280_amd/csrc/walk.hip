@@ -2041,11 +2041,13 @@ void make_exec(const n2v_graph *g, const n2v_exec_opts &o, Exec *E)
     E->search_ratio = o.search_ratio;
     E->sparse_ratio = o.sparse_ratio < 1 ? 1 : o.sparse_ratio;
     // Where hub rows hold a large share of the entries (so of the visits), a
-    // lane's walk soon reaches one and waits while the other lanes go on: two
-    // rejection moves per lane before the wave serves its pending walks.
-    // Otherwise eight, since each return to the wave phase reloads the lanes'
-    // vertex records.
-    E->thread_iters = g->hub_entries * 50 >= g->dg.m && g->hub_entries ? 2u : 8u;
+    // lane's walk soon reaches one and waits while the other lanes go on: one
+    // rejection move per lane before the wave serves its pending walks when
+    // hub rows hold at least 35% of the entries, two from 2%.  Otherwise
+    // eight, since each return to the wave phase reloads the lanes' vertex
+    // records.
+    const uint64_t he = g->hub_entries, m = g->dg.m;
+    E->thread_iters = he && he * 20 >= m * 7 ? 1u : (he && he * 50 >= m ? 2u : 8u);
 }
 
 PlainKey plain_key(const Exec &E, const OneJob &S, const void *ws, uint32_t hub_blocks, bool W, bool C)
